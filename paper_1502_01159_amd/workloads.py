@@ -1,0 +1,224 @@
+"""Seeded synthetic workloads: lattice/physics configurations and particle placements.
+
+This module generates *inputs* only.  It holds none of the method's arithmetic
+(no relaxation times, equilibria, forcing or contact laws); both the HIP
+library and the CPU oracle receive its plain dicts and arrays and derive
+everything else themselves.
+
+The cases stand in for the paper's four studies (Sec. 3): the 2D cavity with a
+hot concentric cylinder (Sec. 3.1, Table 1 case Ra = 1e4, Ar = 2.5), 2D and 3D
+sedimentation of hot isothermal particles (Secs. 3.2, 3.3) and 3D
+thermosensitive particles (Sec. 3.4).  All values are lattice units; gravity
+points along -y in 2D and -z in 3D; every non-periodic face is a no-slip wall.
+
+Particle arrays are (n, 13) float64 rows: x[3] u[3] omega[3] R rho_r T flags,
+flags = 1 (fixed body) | 2 (thermosensitive).
+
+Random numbers come from splitmix64 (Steele, Lea & Flood, 2014) mapped to
+53-bit uniform doubles, so that the placements are reproducible on any host.
+"""
+from __future__ import annotations
+
+import copy
+import math
+
+import numpy as np
+
+FIXED = 1
+THERMO = 2
+
+_M64 = (1 << 64) - 1
+
+
+class SplitMix64:
+    """splitmix64: state += golden gamma; output = mix(state)."""
+
+    def __init__(self, seed: int):
+        self.state = seed & _M64
+
+    def next_u64(self) -> int:
+        self.state = (self.state + 0x9E3779B97F4A7C15) & _M64
+        z = self.state
+        z = ((z ^ (z >> 30)) * 0xBF58476D1CE4E5B9) & _M64
+        z = ((z ^ (z >> 27)) * 0x94D049BB133111EB) & _M64
+        return z ^ (z >> 31)
+
+    def uniform(self) -> float:
+        """Uniform double in [0, 1) with 53 random bits."""
+        return (self.next_u64() >> 11) * (1.0 / 9007199254740992.0)
+
+    def uniforms(self, n: int) -> np.ndarray:
+        return np.array([self.uniform() for _ in range(n)], dtype=np.float64)
+
+
+def _row(x, R, rho_r, T, flags, u=(0.0, 0.0, 0.0), om=(0.0, 0.0, 0.0)):
+    return [x[0], x[1], x[2], u[0], u[1], u[2], om[0], om[1], om[2], R, rho_r, T, float(flags)]
+
+
+def rsa(seed: int, n: int, lo, hi, min_dist: float, max_trials: int = 2_000_000) -> np.ndarray:
+    """Random sequential addition: centres uniform in the box [lo, hi] (per
+    axis), accepted when no earlier centre is closer than ``min_dist``."""
+    rng = SplitMix64(seed)
+    lo = np.asarray(lo, dtype=np.float64)
+    hi = np.asarray(hi, dtype=np.float64)
+    d = lo.size
+    pts = np.empty((n, d))
+    k = 0
+    trials = 0
+    md2 = min_dist * min_dist
+    while k < n:
+        trials += 1
+        if trials > max_trials:
+            raise RuntimeError(f"RSA could not place {n} particles (placed {k})")
+        c = lo + (hi - lo) * np.array([rng.uniform() for _ in range(d)])
+        if k:
+            dd = pts[:k] - c
+            if np.min(np.einsum("ij,ij->i", dd, dd)) < md2:
+                continue
+        pts[k] = c
+        k += 1
+    return pts
+
+
+# --------------------------------------------------------------------------- #
+# Base configurations                                                          #
+# --------------------------------------------------------------------------- #
+
+def annulus_2d(n: int = 64, Ra: float = 1e4, Ar: float = 2.5, Pr: float = 0.71):
+    """Square cavity of side n with a fixed hot cylinder of diameter n/Ar at the
+    centre (Sec. 3.1): walls T = 0, cylinder T = 1, fluid initially 0.5,
+    Ma = 0.1 (uc = 0.1 c_s)."""
+    cfg = dict(
+        name=f"annulus2d_{n}", dim=2, nx=n, ny=n, nz=1, periodic=[0, 0, 0],
+        T_wall=[0.0] * 6, T_init=0.5, T_ref=0.5,
+        Ra=Ra, Pr=Pr, Lc=float(n), uc=0.1 / math.sqrt(3.0), dT_ref=1.0,
+        gravity=0.0, kappa_T=1.0, marker_mode=1, marker_spacing=1.0,
+        E_star=0.0, poisson=0.33, mu_fric=0.3, n_sub=1, beta_p=0.0, c_r=1.0,
+    )
+    c = 0.5 * n - 0.5
+    P = np.array([_row((c, c, 0.0), 0.5 * n / Ar, 1.0, 1.0, FIXED)])
+    return cfg, P
+
+
+def sediment_2d(nx: int = 512, ny: int = 1024, n_disks: int = 100, D: float = 20.0, seed: int = 2,
+                Gr: float = 500.0):
+    """2D sedimentation of hot isothermal disks (Sec. 3.2 stand-in): disks
+    seeded uniformly without overlap in the upper half."""
+    cfg = dict(
+        name=f"sediment2d_{nx}x{ny}_{n_disks}", dim=2, nx=nx, ny=ny, nz=1, periodic=[0, 0, 0],
+        T_wall=[0.0] * 6, T_init=0.0, T_ref=0.0,
+        Ra=0.0, nu=0.04, Pr=0.7, Gr=Gr, Lc=D,
+        gravity=0.0125, kappa_T=1.0, marker_mode=1, marker_spacing=1.0,
+        E_star=52.6, poisson=0.33, mu_fric=0.3, n_sub=6, beta_p=0.0, c_r=1.0,
+    )
+    R = 0.5 * D
+    lo = [R + 1.0, ny / 2 + R + 1.0]
+    hi = [nx - R - 2.0, ny - R - 2.0]
+    pts = rsa(seed, n_disks, lo, hi, D + 1.0)
+    P = np.array([_row((p[0], p[1], 0.0), R, 1.01, 1.0, 0) for p in pts])
+    return cfg, P
+
+
+def sediment_3d(nx: int = 256, ny: int = 256, nz: int = 512, n_spheres: int = 2000, D: float = 12.0,
+                seed: int = 3, Gr: float = 100.0):
+    """3D sedimentation of hot isothermal spheres (Sec. 3.3 stand-in): random
+    sequential addition in the top third-plus of the box."""
+    cfg = dict(
+        name=f"sediment3d_{nx}x{ny}x{nz}_{n_spheres}", dim=3, nx=nx, ny=ny, nz=nz, periodic=[0, 0, 0],
+        T_wall=[0.0] * 6, T_init=0.0, T_ref=0.0,
+        Ra=0.0, nu=0.025, Pr=0.7, Gr=Gr, Lc=D,
+        gravity=4.167e-3, kappa_T=1.0, marker_mode=1, marker_spacing=1.0,
+        E_star=729.0, poisson=0.33, mu_fric=0.3, n_sub=9, beta_p=0.0, c_r=1.0,
+    )
+    R = 0.5 * D
+    lo = [R + 1.0, R + 1.0, nz * 0.68]
+    hi = [nx - R - 2.0, ny - R - 2.0, nz - R - 2.0]
+    pts = rsa(seed, n_spheres, lo, hi, D + 1.0)
+    P = np.array([_row(p, R, 1.05, 1.0, 0) for p in pts])
+    return cfg, P
+
+
+def thermo_3d(n: int = 384, n_spheres: int = 20000, D: float = 10.0, seed: int = 4, Gr: float = 100.0):
+    """3D thermosensitive spheres (Sec. 3.4 stand-in): a jittered lattice of
+    sites filling the upper part of the box, a seeded subset of them kept,
+    initial particle temperature uniform in [0, 1)."""
+    cfg = dict(
+        name=f"thermo3d_{n}_{n_spheres}", dim=3, nx=n, ny=n, nz=n, periodic=[0, 0, 0],
+        T_wall=[0.0] * 6, T_init=0.5, T_ref=0.5,
+        Ra=0.0, nu=0.025, Pr=0.7, Gr=Gr, Lc=D,
+        gravity=4.167e-3, kappa_T=1.0, marker_mode=1, marker_spacing=1.0,
+        E_star=729.0, poisson=0.33, mu_fric=0.3, n_sub=11, beta_p=0.05, c_r=1.0,
+    )
+    R = 0.5 * D
+    lateral = max(1, int(n / (D + 3.714)))           # 28 sites across 384 lu
+    pitch = n / lateral
+    zpitch = D + 1.0
+    top = n - R - 2.0 - 0.5
+    layers = int((top - 0.5 * n) / zpitch) + 1 if n_spheres > lateral * lateral else 1
+    while lateral * lateral * layers < n_spheres:
+        layers += 1
+    sites = []
+    for m in range(layers):
+        z = top - zpitch * m
+        for j in range(lateral):
+            for i in range(lateral):
+                sites.append((-0.5 + pitch * (i + 0.5), -0.5 + pitch * (j + 0.5), z))
+    sites = np.array(sites)
+    if sites[:, 2].min() - R < 0:
+        raise ValueError("lattice of sites does not fit the box")
+    rng = SplitMix64(seed)
+    # seeded permutation (Fisher-Yates) to choose the kept sites
+    idx = list(range(len(sites)))
+    for i in range(len(idx) - 1, 0, -1):
+        j = int(rng.uniform() * (i + 1))
+        idx[i], idx[j] = idx[j], idx[i]
+    keep = sorted(idx[:n_spheres])
+    P = []
+    for s in keep:
+        x = sites[s] + (np.array([rng.uniform(), rng.uniform(), rng.uniform()]) - 0.5)
+        P.append(_row(x, R, 1.05, rng.uniform(), THERMO))
+    return cfg, np.array(P)
+
+
+# --------------------------------------------------------------------------- #
+# The named workloads                                                          #
+# --------------------------------------------------------------------------- #
+
+def workload(name: str):
+    """Named workloads.  Full sizes:
+    c1 annulus 64^2; c2 2D sedimentation 512x1024, 100 disks; c3 3D
+    sedimentation 256x256x512, 2000 spheres; c4 thermosensitive 384^3, 20000
+    spheres.  Small variants (suffix _small) keep the structure for parity
+    runs that the oracle finishes in seconds."""
+    if name == "c1":
+        return annulus_2d(64)
+    if name == "c2":
+        return sediment_2d()
+    if name == "c2_small":
+        return sediment_2d(nx=96, ny=160, n_disks=6, D=16.0, seed=12)
+    if name.startswith("c3"):
+        gr = 100.0
+        if "_gr" in name:
+            gr = float(name.split("_gr")[1])
+        if name.startswith("c3_small"):
+            return sediment_3d(nx=48, ny=40, nz=64, n_spheres=6, D=10.0, seed=13, Gr=gr)
+        return sediment_3d(Gr=gr)
+    if name == "c4":
+        return thermo_3d()
+    if name == "c4_small":
+        return thermo_3d(n=40, n_spheres=10, D=8.0, seed=14)
+    raise KeyError(name)
+
+
+def with_overrides(cfg: dict, **kw) -> dict:
+    out = copy.deepcopy(cfg)
+    out.update(kw)
+    return out
+
+
+def perturbed_populations(seed: int, Q: int, N: int, weights, base: float, amp: float) -> np.ndarray:
+    """Random populations w_a (base + amp * U(-1, 1)) for single-step tests
+    that start from a non-equilibrium state."""
+    rng = np.random.default_rng(seed)
+    w = np.asarray(weights, dtype=np.float64).reshape(Q, 1)
+    return w * (base + amp * (2.0 * rng.random((Q, N)) - 1.0))
