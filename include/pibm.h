@@ -1,0 +1,192 @@
+/*
+ * pibm.h -- C ABI of the MI355X (gfx950) library for the coupled thermal
+ * lattice-Boltzmann / particulate-immersed-boundary / DEM time step of
+ * Zhang, Yuan, Trias, Yu, Tan & Oliva, "Particulate immersed boundary method
+ * for complex fluid-particle interaction problems with heat transfer"
+ * (arXiv 1502.01159).
+ *
+ * One context = one simulation on one GPU.  The caller owns the device
+ * workspace and the HIP stream; the library carves every buffer out of the
+ * workspace and allocates no device memory of its own.  Host arrays passed in
+ * are copied; the library keeps no host pointer after a call returns.
+ * Contexts are not thread-safe: one host thread per context at a time.
+ *
+ * Units are lattice units throughout (h = dt = c = 1, reference fluid
+ * density 1).  Lattice nodes are (i, j, k) with 0 <= i < nx, x fastest in
+ * memory; non-periodic faces are no-slip walls half-way between the last node
+ * and its missing neighbour (at -1/2 and n - 1/2).  Gravity acts along -y in
+ * 2D and -z in 3D.
+ *
+ * Every call returns a pibm_status.  No C++ exception crosses this boundary.
+ * After an error the context stays usable except after PIBM_EDEVICE.
+ */
+#ifndef PIBM_H
+#define PIBM_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct pibm_ctx pibm_ctx;
+
+typedef enum {
+    PIBM_OK = 0,
+    PIBM_EINVAL = -1,    /* bad parameter, size, pointer or workspace too small */
+    PIBM_ENOMEM = -2,    /* a device-side capacity (contacts, neighbours) was exceeded */
+    PIBM_EDEVICE = -3,   /* a HIP runtime call failed; the context must be destroyed */
+    PIBM_EUNSTABLE = -4, /* the device watchdog saw a NaN, |u| > 0.4, a stale neighbour list
+                            or a particle outside the domain */
+    PIBM_EOVERLAP = -5,  /* initial particles overlap */
+    PIBM_ESTATE = -6     /* call not valid in the current state (e.g. wrong checkpoint) */
+} pibm_status;
+
+/* Storage of the distributions.  Every variant stores deviations from the
+ * rest state (f - w rho0, g - w T_ref) and collides in the compute type:
+ * F32 stores and computes in float, F64 in double, F16DEV / BF16DEV store
+ * 16-bit deviations scaled by 1/w and compute in float. */
+typedef enum {
+    PIBM_STORE_F32 = 0,
+    PIBM_STORE_F64 = 1,
+    PIBM_STORE_F16DEV = 2,
+    PIBM_STORE_BF16DEV = 3
+} pibm_storage;
+
+/* Lagrangian-point (marker) weights:
+ *   SURFACE: the body surface element, pi D / N (2D) or pi D^2 / N (3D);
+ *   PAPER:   the cross-section of a Lagrangian particle of diameter equal to
+ *            the marker spacing s, pi s^2 / 4 in 3D and s per unit depth in
+ *            2D (Sec. 2.2, after Eq. lbm12.6) -- the default;
+ *   POINT:   one point at the body centre carrying the body cross-section
+ *            (pi D^2 / 4 in 3D, D in 2D): the paper's sub-grid particle. */
+typedef enum { PIBM_MARKERS_SURFACE = 0, PIBM_MARKERS_PAPER = 1, PIBM_MARKERS_POINT = 2 } pibm_markers;
+
+/* Problem statement (Sec. 2): lattice, walls, Ra/Pr or nu/Gr, particles'
+ * material.  Fields are read once by pibm_init. */
+typedef struct pibm_params {
+    int dim;                 /* 2 (D2Q9 + D2Q5) or 3 (D3Q19 + D3Q7) */
+    int nx, ny, nz;          /* nodes per axis; nz = 1 in 2D */
+    int periodic[3];         /* non-zero: periodic axis; zero: two walls */
+    int storage;             /* pibm_storage */
+    double T_wall[6];        /* Dirichlet wall temperature per face: -x,+x,-y,+y,-z,+z */
+    double T_init;           /* initial fluid temperature (fluid at rest, rho = 1) */
+    double T_ref;            /* Boussinesq reference temperature */
+    /* Relaxation times.  If Ra > 0: Eqs. (lbm2.6), (lbm2.7) with
+     * nu = sqrt(Pr) Lc uc / sqrt(Ra), alpha = Lc uc / sqrt(Pr Ra) and
+     * g beta = uc^2 / (Lc dT_ref).  Otherwise nu is given, alpha = nu / Pr
+     * and g beta = Gr nu^2 / Lc^3 (Gr on the length Lc).  Then
+     * tau_f = 3 nu + 1/2 and tau_g = alpha / c_sg^2 + 1/2 (c_sg^2 = 1/3 for
+     * D2Q5, 1/4 for D3Q7).  tau_f / tau_g > 0 override the derived values;
+     * gbeta is used instead of the derived value when gbeta_set != 0. */
+    double Ra, Pr, Lc, uc, dT_ref;
+    double nu, Gr;
+    double tau_f, tau_g;
+    double gbeta;
+    int gbeta_set;
+    int marker_mode;         /* pibm_markers */
+    double marker_spacing;   /* lattice units; <= 0 means 1 */
+    double gravity;          /* particle gravity magnitude (lu / step^2) */
+    double kappa_T;          /* thermal exchange prefactor of Q_l = 2 kappa_T (T_p - T_l) */
+    double E_star;           /* Hertz effective modulus E* (same material for walls) */
+    double poisson;          /* Poisson ratio (enters G*) */
+    double mu_fric;          /* Coulomb friction coefficient */
+    int n_sub;               /* DEM sub-steps per lattice step (>= 1) */
+    double beta_p;           /* thermosensitive particles: rho_p(T) = rho_r (1 - beta_p (T - T_ref)) */
+    double c_r;              /* particle / fluid volumetric heat-capacity ratio */
+    double skin;             /* DEM neighbour-list skin (lu); <= 0 means 1 */
+} pibm_params;
+
+enum { PIBM_FIXED = 1, PIBM_THERMO = 2 };
+
+/* One particle: centre x, velocity u, angular velocity omega (2D: omega[2]),
+ * accumulated rotation theta (diagnostic), radius R, density ratio rho_r =
+ * rho_p / rho_f, temperature T, flags (PIBM_FIXED: not integrated;
+ * PIBM_THERMO: temperature follows the lumped heat balance). */
+typedef struct pibm_particle {
+    double x[3], u[3], omega[3], theta[3];
+    double R, rho_r, T;
+    int flags;
+    int reserved;
+} pibm_particle;
+
+/* Bytes of device workspace pibm_init needs for these parameters and
+ * particles (radii decide the marker counts).  Returns 0 on invalid input. */
+size_t pibm_workspace_bytes(const pibm_params *p, const pibm_particle *particles, int n_particles);
+
+/* Create a context.  dev_workspace: device pointer (>= pibm_workspace_bytes,
+ * 256-byte aligned) owned by the caller and borrowed until pibm_destroy;
+ * hip_stream: the caller's hipStream_t (NULL = default stream) on which all
+ * work is queued.  Validates tau > 1/2, sizes, particle overlap and
+ * containment; fills f = w rho0, g = w T_init; uploads particles.  Returns
+ * after the uploads completed. */
+int pibm_init(pibm_ctx **out, const pibm_params *p, const pibm_particle *particles, int n_particles,
+              void *dev_workspace, size_t workspace_bytes, void *hip_stream);
+
+/* Advance n_steps coupled time steps (Sec. 2): stream + PIBM exchange +
+ * spreading + forced BGK collision for f and g, then the DEM sub-steps and
+ * the thermosensitive update.  Asynchronous on the context's stream (no host
+ * synchronisation); returns the first device error seen by an earlier
+ * pibm_sync / pibm_particles / pibm_fields call, if any. */
+int pibm_step(pibm_ctx *ctx, int n_steps);
+
+/* Wait for the stream and return the device watchdog status. */
+int pibm_sync(pibm_ctx *ctx);
+
+/* Copy the particle state to out[cap] (cap >= n_particles); if fth is not
+ * NULL, also the last step's reactions, 8 doubles per particle:
+ * F[3] tau[3] H sum_l (T_p - T_l) A_l (Eq. lbm13; H = heat given to the
+ * fluid).  Synchronises. */
+int pibm_particles(pibm_ctx *ctx, pibm_particle *out, double *fth, int cap);
+
+/* Replace the particle state (same count and radii as at init). */
+int pibm_set_particles(pibm_ctx *ctx, const pibm_particle *p, int n);
+
+/* Host copies of the macroscopic fields that the next collision would use:
+ * rho[N], u[3 N] (node-major, 3 components), T[N]; any may be NULL.  The
+ * state is not advanced.  Synchronises. */
+int pibm_fields(pibm_ctx *ctx, double *rho, double *u, double *T);
+
+/* Distributions of the current state as absolute values, q-major:
+ * f[Q][N], g[Qg][N] (Q = 9/19, Qg = 5/7).  Synchronises. */
+int pibm_get_populations(pibm_ctx *ctx, double *f, double *g);
+int pibm_set_populations(pibm_ctx *ctx, const double *f, const double *g);
+
+/* Number of lattice nodes, markers, and the step counter. */
+long long pibm_num_nodes(const pibm_ctx *ctx);
+long long pibm_num_markers(const pibm_ctx *ctx);
+long long pibm_step_count(const pibm_ctx *ctx);
+
+/* Derived parameters: out[0..4] = tau_f, tau_g, g beta, nu, alpha. */
+int pibm_derived(const pibm_ctx *ctx, double *out);
+
+/* Checkpoint: a versioned blob of parameters, step counter, distributions,
+ * particles and contact history.  pibm_save with host_buf == NULL reports
+ * the size in *used.  pibm_load requires identical parameters. */
+int pibm_save(pibm_ctx *ctx, void *host_buf, size_t cap, size_t *used);
+int pibm_load(pibm_ctx *ctx, const void *host_buf, size_t n);
+
+/* Phase profiling.  While enabled, pibm_step records a pair of HIP events
+ * on the context's stream around each phase of every step:
+ *   PIBM_PHASE_MARKERS  Lagrangian points: interpolation, exchange, reactions;
+ *   PIBM_PHASE_BIN      particle -> lattice-tile binning;
+ *   PIBM_PHASE_LATTICE  the fused stream / spreading / collision kernel;
+ *   PIBM_PHASE_DEM      neighbour lists and the DEM sub-steps.
+ * pibm_profile_read synchronises, returns per phase the summed elapsed
+ * milliseconds ms[PIBM_NPHASE] and the number of timed phase executions
+ * count[PIBM_NPHASE] since the previous read, and resets them. */
+enum { PIBM_PHASE_MARKERS = 0, PIBM_PHASE_BIN = 1, PIBM_PHASE_LATTICE = 2, PIBM_PHASE_DEM = 3, PIBM_NPHASE = 4 };
+int pibm_profile(pibm_ctx *ctx, int enable);
+int pibm_profile_read(pibm_ctx *ctx, double *ms, long long *count);
+
+/* Release the context (not the caller's workspace or stream). */
+int pibm_destroy(pibm_ctx *ctx);
+
+/* Static description of a status code. */
+const char *pibm_strerror(int status);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PIBM_H */

@@ -1,0 +1,928 @@
+// pibm.hip -- host runtime and C ABI of the gfx950 LBM-PIBM-DEM library.
+//
+// Per coupled step, all on the caller's stream:
+//   K2 k_markers    Lagrangian points: interpolation, exchange, reactions
+//   K3 k_bin        particles -> lattice tiles (count, scan, scatter)
+//   K1 k_lbm        fused stream + spreading + buoyancy + forced BGK (f, g)
+//   K4 k_cells      DEM cell list + Verlet lists
+//   K5 k_dem x n    DEM sub-steps (+ thermosensitive update on the last)
+// then the A/B lattices swap.  Nothing here allocates device memory: every
+// buffer is carved from the caller's workspace.
+#include "pibm_device.h"
+#include "../../include/pibm.h"
+
+#include <algorithm>
+#include <cmath>
+#include <cstdint>
+#include <cstring>
+#include <new>
+#include <vector>
+
+using namespace pibm;
+
+namespace {
+
+constexpr size_t ALIGN = 256;
+size_t up(size_t v) { return (v + ALIGN - 1) / ALIGN * ALIGN; }
+
+enum Region {
+    R_FA, R_GA, R_FB, R_GB, R_PART0, R_PART1, R_REACT, R_TMPL, R_TMPL_START, R_TMPL_REXT, R_MK_START, R_MK,
+    R_TCOUNT, R_TSTART, R_TFILL, R_TITEMS, R_CCOUNT, R_CSTART, R_CFILL, R_CITEMS, R_NBR, R_NBRN, R_XREF,
+    R_HID0, R_HXI0, R_HN0, R_HID1, R_HXI1, R_HN1, R_ERR, R_COUNT
+};
+
+struct Template {
+    double R;
+    std::vector<double> off;       // 4 per marker: r_x, r_y, r_z, A
+};
+
+struct Plan {
+    int dim, Q, QG;
+    long long N, Ns;
+    size_t ssize, tsize;           // storage and compute type sizes
+    int ntx, nty, ntz, ntiles;
+    int TX, TY, TZ;
+    int ncx, ncy, ncz, ncells;
+    double cwx, cwy, cwz, skin;
+    int np;
+    std::vector<Template> tmpls;
+    std::vector<int> ptmpl;        // template of each particle
+    std::vector<int> mk_start;     // np + 1
+    long long nmk, ntmpl_mk;
+    long long tile_cap;
+    size_t off[R_COUNT + 1];
+};
+
+double derive_csg2(int dim) { return dim == 2 ? 1.0 / 3.0 : 0.25; }
+
+struct Derived {
+    double tau_f, tau_g, gbeta, nu, alpha;
+};
+
+// Relaxation times: Eqs. (lbm2.6), (lbm2.7) when Ra > 0, else from nu and Gr.
+Derived derive(const pibm_params &p)
+{
+    Derived d{};
+    if (p.Ra > 0) {
+        d.nu = std::sqrt(p.Pr) * p.Lc * p.uc / std::sqrt(p.Ra);
+        d.alpha = p.Lc * p.uc / std::sqrt(p.Pr * p.Ra);
+        d.gbeta = p.uc * p.uc / (p.Lc * (p.dT_ref > 0 ? p.dT_ref : 1.0));
+    } else {
+        d.nu = p.nu;
+        d.alpha = p.Pr > 0 ? p.nu / p.Pr : 0.0;
+        d.gbeta = p.Lc > 0 ? p.Gr * p.nu * p.nu / (p.Lc * p.Lc * p.Lc) : 0.0;
+    }
+    d.tau_f = 3.0 * d.nu + 0.5;
+    d.tau_g = d.alpha / derive_csg2(p.dim) + 0.5;
+    if (p.tau_f > 0) { d.tau_f = p.tau_f; d.nu = (p.tau_f - 0.5) / 3.0; }
+    if (p.tau_g > 0) { d.tau_g = p.tau_g; d.alpha = (p.tau_g - 0.5) * derive_csg2(p.dim); }
+    if (p.gbeta_set) d.gbeta = p.gbeta;
+    return d;
+}
+
+// Lagrangian points on the body surface: a ring of round(pi D / s) points
+// (2D) or a Fibonacci sphere of round(pi D^2 / s^2) points (3D); weights per
+// pibm_markers.
+Template make_template(int dim, double R, int mode, double s)
+{
+    const double pi = 3.14159265358979323846;
+    Template t;
+    t.R = R;
+    const double D = 2.0 * R;
+    if (mode == PIBM_MARKERS_POINT) {
+        t.off = {0.0, 0.0, 0.0, dim == 2 ? D : 0.25 * pi * D * D};
+        return t;
+    }
+    int n = dim == 2 ? (int)std::lround(pi * D / s) : (int)std::lround(pi * D * D / (s * s));
+    if (n < 1) n = 1;
+    t.off.resize((size_t)4 * n);
+    const double golden = pi * (3.0 - std::sqrt(5.0));
+    for (int k = 0; k < n; ++k) {
+        double *o = &t.off[(size_t)4 * k];
+        if (dim == 2) {
+            const double th = 2.0 * pi * k / n;
+            o[0] = R * std::cos(th); o[1] = R * std::sin(th); o[2] = 0.0;
+            o[3] = mode == PIBM_MARKERS_SURFACE ? pi * D / n : s;
+        } else {
+            const double z = 1.0 - (2.0 * k + 1.0) / n;
+            const double rr = std::sqrt(1.0 - z * z);
+            const double ph = k * golden;
+            o[0] = R * rr * std::cos(ph); o[1] = R * rr * std::sin(ph); o[2] = R * z;
+            o[3] = mode == PIBM_MARKERS_SURFACE ? pi * D * D / n : 0.25 * pi * s * s;
+        }
+    }
+    return t;
+}
+
+int tiles_along(double rext, int n, int T)
+{
+    const int span = (int)std::ceil(2.0 * rext) + 5;
+    return std::min((n + T - 1) / T, (span - 1) / T + 2);
+}
+
+int check_params(const pibm_params *p)
+{
+    if (!p) return PIBM_EINVAL;
+    if (p->dim != 2 && p->dim != 3) return PIBM_EINVAL;
+    if (p->nx < 1 || p->ny < 1 || p->nz < 1) return PIBM_EINVAL;
+    if (p->dim == 2 && p->nz != 1) return PIBM_EINVAL;
+    if ((long long)p->nx * p->ny * p->nz > (1LL << 31) - 1) return PIBM_EINVAL;
+    if (p->storage < PIBM_STORE_F32 || p->storage > PIBM_STORE_BF16DEV) return PIBM_EINVAL;
+    if (p->marker_mode < 0 || p->marker_mode > 2) return PIBM_EINVAL;
+    if (p->n_sub < 1) return PIBM_EINVAL;
+    const Derived d = derive(*p);
+    if (!(d.tau_f > 0.5) || !(d.tau_g > 0.5)) return PIBM_EINVAL;
+    if (!std::isfinite(d.gbeta)) return PIBM_EINVAL;
+    return PIBM_OK;
+}
+
+int make_plan(const pibm_params *p, const pibm_particle *pt, int np, Plan &P)
+{
+    int st = check_params(p);
+    if (st) return st;
+    if (np < 0 || (np > 0 && !pt)) return PIBM_EINVAL;
+    P.dim = p->dim;
+    P.Q = p->dim == 2 ? 9 : 19;
+    P.QG = p->dim == 2 ? 5 : 7;
+    P.N = (long long)p->nx * p->ny * p->nz;
+    P.Ns = (P.N + 63) / 64 * 64;
+    P.ssize = p->storage == PIBM_STORE_F64 ? 8 : (p->storage == PIBM_STORE_F32 ? 4 : 2);
+    P.tsize = p->storage == PIBM_STORE_F64 ? 8 : 4;
+    P.TX = TILE_X;
+    P.TY = p->dim == 3 ? Tile<3>::Y : Tile<2>::Y;
+    P.TZ = p->dim == 3 ? Tile<3>::Z : Tile<2>::Z;
+    P.ntx = (p->nx + P.TX - 1) / P.TX;
+    P.nty = (p->ny + P.TY - 1) / P.TY;
+    P.ntz = (p->nz + P.TZ - 1) / P.TZ;
+    P.ntiles = P.ntx * P.nty * P.ntz;
+    P.np = np;
+    const double s = p->marker_spacing > 0 ? p->marker_spacing : 1.0;
+    P.skin = p->skin > 0 ? p->skin : 1.0;
+    double Rmax = 0.0;
+    P.tmpls.clear();
+    P.ptmpl.assign(np, 0);
+    for (int i = 0; i < np; ++i) {
+        const double R = pt[i].R;
+        if (!(R > 0) || !std::isfinite(R)) return PIBM_EINVAL;
+        Rmax = std::max(Rmax, R);
+        int k = -1;
+        for (size_t t = 0; t < P.tmpls.size(); ++t)
+            if (P.tmpls[t].R == R) { k = (int)t; break; }
+        if (k < 0) {
+            P.tmpls.push_back(make_template(p->dim, R, p->marker_mode, s));
+            k = (int)P.tmpls.size() - 1;
+        }
+        P.ptmpl[i] = k;
+    }
+    // markers
+    P.mk_start.assign(np + 1, 0);
+    P.ntmpl_mk = 0;
+    for (auto &t : P.tmpls) P.ntmpl_mk += (long long)t.off.size() / 4;
+    for (int i = 0; i < np; ++i) P.mk_start[i + 1] = P.mk_start[i] + (int)(P.tmpls[P.ptmpl[i]].off.size() / 4);
+    P.nmk = P.mk_start[np];
+    // tile-list capacity: every tile a particle's footprint can touch
+    P.tile_cap = 0;
+    for (int i = 0; i < np; ++i) {
+        const double re = p->marker_mode == PIBM_MARKERS_POINT ? 0.0 : pt[i].R;
+        if ((int)std::ceil(2.0 * re) + 5 > (MAXT_AXIS - 1) * P.TY) return PIBM_EINVAL;
+        long long c = (long long)tiles_along(re, p->nx, P.TX) * tiles_along(re, p->ny, P.TY);
+        if (p->dim == 3) c *= tiles_along(re, p->nz, P.TZ);
+        P.tile_cap += c;
+    }
+    // DEM cells of width >= 2 Rmax + skin
+    const double cs = std::max(2.0 * Rmax + P.skin, 1.0);
+    P.ncx = std::max(1, (int)std::floor(p->nx / cs));
+    P.ncy = std::max(1, (int)std::floor(p->ny / cs));
+    P.ncz = p->dim == 3 ? std::max(1, (int)std::floor(p->nz / cs)) : 1;
+    P.cwx = (double)p->nx / P.ncx;
+    P.cwy = (double)p->ny / P.ncy;
+    P.cwz = p->dim == 3 ? (double)p->nz / P.ncz : 1.0;
+    P.ncells = P.ncx * P.ncy * P.ncz;
+    // layout
+    const long long npa = std::max(np, 1);
+    size_t sz[R_COUNT];
+    const size_t fbytes = (size_t)P.Q * P.Ns * P.ssize, gbytes = (size_t)P.QG * P.Ns * P.ssize;
+    sz[R_FA] = fbytes; sz[R_GA] = gbytes; sz[R_FB] = fbytes; sz[R_GB] = gbytes;
+    sz[R_PART0] = sz[R_PART1] = npa * sizeof(DevParticle);
+    sz[R_REACT] = npa * sizeof(DevReact);
+    sz[R_TMPL] = std::max(P.ntmpl_mk, 1LL) * sizeof(double4);
+    sz[R_TMPL_START] = (P.tmpls.size() + 1) * sizeof(int);
+    sz[R_TMPL_REXT] = (P.tmpls.size() + 1) * sizeof(double);
+    sz[R_MK_START] = (npa + 1) * sizeof(int);
+    sz[R_MK] = std::max(P.nmk, 1LL) * (p->storage == PIBM_STORE_F64 ? sizeof(MarkerRec<double>) : sizeof(MarkerRec<float>));
+    sz[R_TCOUNT] = (size_t)P.ntiles * sizeof(int);
+    sz[R_TSTART] = (size_t)(P.ntiles + 1) * sizeof(int);
+    sz[R_TFILL] = (size_t)P.ntiles * sizeof(int);
+    sz[R_TITEMS] = std::max(P.tile_cap, 1LL) * sizeof(int);
+    sz[R_CCOUNT] = (size_t)P.ncells * sizeof(int);
+    sz[R_CSTART] = (size_t)(P.ncells + 1) * sizeof(int);
+    sz[R_CFILL] = (size_t)P.ncells * sizeof(int);
+    sz[R_CITEMS] = npa * sizeof(int);
+    sz[R_NBR] = npa * MAXN * sizeof(int);
+    sz[R_NBRN] = npa * sizeof(int);
+    sz[R_XREF] = npa * 3 * sizeof(double);
+    sz[R_HID0] = sz[R_HID1] = npa * MAXC * sizeof(int);
+    sz[R_HXI0] = sz[R_HXI1] = npa * MAXC * 3 * sizeof(double);
+    sz[R_HN0] = sz[R_HN1] = npa * sizeof(int);
+    sz[R_ERR] = 64;
+    size_t o = 0;
+    for (int r = 0; r < R_COUNT; ++r) { P.off[r] = o; o += up(sz[r]); }
+    P.off[R_COUNT] = o;
+    return PIBM_OK;
+}
+
+int check_particles(const pibm_params *p, const pibm_particle *pt, int np)
+{
+    const int nn[3] = {p->nx, p->ny, p->nz};
+    double Rmax = 0;
+    for (int i = 0; i < np; ++i) {
+        for (int d = 0; d < p->dim; ++d) {
+            if (!std::isfinite(pt[i].x[d]) || !std::isfinite(pt[i].u[d])) return PIBM_EINVAL;
+            if (!p->periodic[d] && (pt[i].x[d] - pt[i].R < -0.5 || pt[i].x[d] + pt[i].R > nn[d] - 0.5))
+                return PIBM_EINVAL;
+        }
+        if (!(pt[i].rho_r > 0)) return PIBM_EINVAL;
+        Rmax = std::max(Rmax, pt[i].R);
+    }
+    // overlap check on a uniform grid of cells >= 2 Rmax
+    const double cs = std::max(2.0 * Rmax, 1.0);
+    int nc[3] = {1, 1, 1};
+    for (int d = 0; d < p->dim; ++d) nc[d] = std::max(1, (int)std::floor(nn[d] / cs));
+    auto cell = [&](const double *x, int *c) {
+        for (int d = 0; d < 3; ++d) {
+            if (d >= p->dim) { c[d] = 0; continue; }
+            double y = x[d] + 0.5;
+            if (p->periodic[d]) { y = std::fmod(y, (double)nn[d]); if (y < 0) y += nn[d]; }
+            int v = (int)std::floor(y / ((double)nn[d] / nc[d]));
+            c[d] = std::min(std::max(v, 0), nc[d] - 1);
+        }
+    };
+    std::vector<std::vector<int>> cells((size_t)nc[0] * nc[1] * nc[2]);
+    for (int i = 0; i < np; ++i) {
+        int c[3];
+        cell(pt[i].x, c);
+        cells[((size_t)c[2] * nc[1] + c[1]) * nc[0] + c[0]].push_back(i);
+    }
+    for (int i = 0; i < np; ++i) {
+        int c[3];
+        cell(pt[i].x, c);
+        for (int dz = (p->dim == 3 ? -1 : 0); dz <= (p->dim == 3 ? 1 : 0); ++dz)
+            for (int dy = -1; dy <= 1; ++dy)
+                for (int dx = -1; dx <= 1; ++dx) {
+                    int cc[3] = {c[0] + dx, c[1] + dy, c[2] + dz}, ok = 1;
+                    for (int d = 0; d < 3; ++d) {
+                        if (cc[d] < 0 || cc[d] >= nc[d]) {
+                            if (d < p->dim && p->periodic[d]) cc[d] = (cc[d] + nc[d]) % nc[d];
+                            else ok = 0;
+                        }
+                    }
+                    if (!ok) continue;
+                    for (int j : cells[((size_t)cc[2] * nc[1] + cc[1]) * nc[0] + cc[0]]) {
+                        if (j <= i) continue;
+                        double d2 = 0;
+                        for (int d = 0; d < p->dim; ++d) {
+                            double dd = pt[j].x[d] - pt[i].x[d];
+                            if (p->periodic[d]) {
+                                if (dd > 0.5 * nn[d]) dd -= nn[d];
+                                else if (dd < -0.5 * nn[d]) dd += nn[d];
+                            }
+                            d2 += dd * dd;
+                        }
+                        const double lim = pt[i].R + pt[j].R - 1e-9;
+                        if (d2 < lim * lim) return PIBM_EOVERLAP;
+                    }
+                }
+    }
+    return PIBM_OK;
+}
+
+}  // namespace
+
+struct pibm_ctx {
+    pibm_params p;
+    Plan P;
+    Derived d;
+    hipStream_t stream;
+    char *ws;
+    size_t ws_bytes;
+    int cur;        // lattice copy holding the current state (0 = A, 1 = B)
+    int pcur;       // particle buffer holding the current state
+    int hcur;       // contact-history buffer holding the current state
+    long long step;
+    int sticky;
+    int device_lost;
+    // phase profiling: pairs of events recorded around each phase's launches
+    int prof_on = 0;
+    std::vector<hipEvent_t> ev_free;
+    std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_rec[PIBM_NPHASE];
+    void *r(int reg) const { return ws + P.off[reg]; }
+};
+
+namespace {
+
+template <class T> LbmArgs<T> lbm_args(const pibm_ctx *c)
+{
+    LbmArgs<T> a{};
+    a.nx = c->p.nx; a.ny = c->p.ny; a.nz = c->p.nz;
+    for (int d = 0; d < 3; ++d) a.per[d] = c->p.periodic[d] ? 1 : 0;
+    a.Ns = c->P.Ns;
+    a.ntx = c->P.ntx; a.nty = c->P.nty; a.ntz = c->P.ntz; a.ntiles = c->P.ntiles;
+    a.omf = 1.0 / c->d.tau_f;
+    a.omg = 1.0 / c->d.tau_g;
+    a.gf = 1.0 - 0.5 / c->d.tau_f;
+    a.gg = 1.0 - 0.5 / c->d.tau_g;
+    a.gbeta = c->d.gbeta;
+    a.Tref = c->p.T_ref;
+    for (int k = 0; k < 6; ++k) a.tw[k] = c->p.T_wall[k] - c->p.T_ref;
+    const int src = c->cur;
+    a.fA = c->r(src ? R_FB : R_FA);
+    a.gA = c->r(src ? R_GB : R_GA);
+    a.fB = c->r(src ? R_FA : R_FB);
+    a.gB = c->r(src ? R_GA : R_GB);
+    a.tile_start = (const int *)c->r(R_TSTART);
+    a.tile_items = (const int *)c->r(R_TITEMS);
+    a.mk_start = (const int *)c->r(R_MK_START);
+    a.mk = (const MarkerRec<T> *)c->r(R_MK);
+    a.err = (int *)c->r(R_ERR);
+    a.macro = nullptr;
+    a.step = (uint32_t)c->step;
+    return a;
+}
+
+int hip_ok(pibm_ctx *c, hipError_t e)
+{
+    if (e == hipSuccess) return PIBM_OK;
+    if (c) c->device_lost = 1;
+    return PIBM_EDEVICE;
+}
+
+template <int DIM, class SF>
+int launch_markers(pibm_ctx *c, bool reactions)
+{
+    using T = typename SF::T;
+    if (c->P.np == 0) return PIBM_OK;
+    MkArgs<T> m{};
+    m.lb = lbm_args<T>(c);
+    m.part = (const DevParticle *)c->r(c->pcur ? R_PART1 : R_PART0);
+    m.tmpl = (const double4 *)c->r(R_TMPL);
+    m.tmpl_start = (const int *)c->r(R_TMPL_START);
+    m.mk_start = (const int *)c->r(R_MK_START);
+    m.mk = (MarkerRec<T> *)c->r(R_MK);
+    m.react = reactions ? (DevReact *)c->r(R_REACT) : nullptr;
+    m.kappa = c->p.kappa_T;
+    m.Tref = c->p.T_ref;
+    hipLaunchKernelGGL((k_markers<DIM, SF>), dim3(c->P.np), dim3(256), 0, c->stream, m);
+    return hip_ok(c, hipGetLastError());
+}
+
+BinArgs bin_args(pibm_ctx *c)
+{
+    BinArgs b{};
+    b.dim = c->p.dim; b.nx = c->p.nx; b.ny = c->p.ny; b.nz = c->p.nz;
+    for (int d = 0; d < 3; ++d) b.per[d] = c->p.periodic[d] ? 1 : 0;
+    b.TX = c->P.TX; b.TY = c->P.TY; b.TZ = c->P.TZ;
+    b.ntx = c->P.ntx; b.nty = c->P.nty; b.ntz = c->P.ntz;
+    b.np = c->P.np;
+    b.part = (const DevParticle *)c->r(c->pcur ? R_PART1 : R_PART0);
+    b.tmpl_rext = (const double *)c->r(R_TMPL_REXT);
+    b.tile_count = (int *)c->r(R_TCOUNT);
+    b.tile_start = (int *)c->r(R_TSTART);
+    b.tile_fill = (int *)c->r(R_TFILL);
+    b.tile_items = (int *)c->r(R_TITEMS);
+    b.err = (int *)c->r(R_ERR);
+    return b;
+}
+
+int launch_bin(pibm_ctx *c)
+{
+    if (c->P.np == 0) return PIBM_OK;
+    BinArgs b = bin_args(c);
+    const int nt = c->P.ntiles;
+    hipLaunchKernelGGL(k_fill_int, dim3(std::min(1024, (nt + 255) / 256)), dim3(256), 0, c->stream, b.tile_count, (long long)nt, 0);
+    const int gb = (c->P.np + 127) / 128;
+    hipLaunchKernelGGL((k_bin<false>), dim3(gb), dim3(128), 0, c->stream, b);
+    hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, c->stream, (const int *)b.tile_count, b.tile_start, b.tile_fill, nt);
+    hipLaunchKernelGGL((k_bin<true>), dim3(gb), dim3(128), 0, c->stream, b);
+    return hip_ok(c, hipGetLastError());
+}
+
+template <int DIM, class SF, bool MACRO>
+int launch_lbm(pibm_ctx *c)
+{
+    using T = typename SF::T;
+    LbmArgs<T> a = lbm_args<T>(c);
+    if (MACRO) a.macro = (T *)c->r(c->cur ? R_FA : R_FB);   // the idle copy holds the output
+    hipLaunchKernelGGL((k_lbm<DIM, SF, MACRO>), dim3(c->P.ntiles), dim3(LBM_THREADS), 0, c->stream, a);
+    return hip_ok(c, hipGetLastError());
+}
+
+DemArgs dem_args(pibm_ctx *c)
+{
+    DemArgs a{};
+    a.dim = c->p.dim; a.nx = c->p.nx; a.ny = c->p.ny; a.nz = c->p.nz;
+    for (int d = 0; d < 3; ++d) a.per[d] = c->p.periodic[d] ? 1 : 0;
+    a.np = c->P.np;
+    a.ncx = c->P.ncx; a.ncy = c->P.ncy; a.ncz = c->P.ncz;
+    a.cwx = c->P.cwx; a.cwy = c->P.cwy; a.cwz = c->P.cwz;
+    a.skin = c->P.skin;
+    a.react = (const DevReact *)c->r(R_REACT);
+    a.cell_count = (int *)c->r(R_CCOUNT);
+    a.cell_start = (int *)c->r(R_CSTART);
+    a.cell_fill = (int *)c->r(R_CFILL);
+    a.cell_items = (int *)c->r(R_CITEMS);
+    a.nbr = (int *)c->r(R_NBR);
+    a.nbr_n = (int *)c->r(R_NBRN);
+    a.xref = (double *)c->r(R_XREF);
+    const double E = c->p.E_star, nu = c->p.poisson;
+    a.E = E;
+    a.G = (1.0 - nu) * E / (2.0 * (2.0 - nu));
+    a.mu = c->p.mu_fric;
+    a.dts = 1.0 / c->p.n_sub;
+    a.gravity = c->p.gravity;
+    a.beta_p = c->p.beta_p;
+    a.c_r = c->p.c_r;
+    a.Tref = c->p.T_ref;
+    a.err = (int *)c->r(R_ERR);
+    return a;
+}
+
+int launch_dem(pibm_ctx *c)
+{
+    if (c->P.np == 0) return PIBM_OK;
+    DemArgs a = dem_args(c);
+    const int gb = (c->P.np + 127) / 128;
+    a.cur = (const DevParticle *)c->r(c->pcur ? R_PART1 : R_PART0);
+    hipLaunchKernelGGL(k_fill_int, dim3(std::min(1024, (c->P.ncells + 255) / 256)), dim3(256), 0, c->stream,
+                       a.cell_count, (long long)c->P.ncells, 0);
+    hipLaunchKernelGGL((k_cells<false>), dim3(gb), dim3(128), 0, c->stream, a);
+    hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, c->stream, (const int *)a.cell_count, a.cell_start, a.cell_fill,
+                       c->P.ncells);
+    hipLaunchKernelGGL((k_cells<true>), dim3(gb), dim3(128), 0, c->stream, a);
+    hipLaunchKernelGGL(k_neighbours, dim3(gb), dim3(128), 0, c->stream, a);
+    for (int s = 0; s < c->p.n_sub; ++s) {
+        a.cur = (const DevParticle *)c->r(c->pcur ? R_PART1 : R_PART0);
+        a.nxt = (DevParticle *)c->r(c->pcur ? R_PART0 : R_PART1);
+        a.hid_in = (const int *)c->r(c->hcur ? R_HID1 : R_HID0);
+        a.hxi_in = (const double *)c->r(c->hcur ? R_HXI1 : R_HXI0);
+        a.hn_in = (const int *)c->r(c->hcur ? R_HN1 : R_HN0);
+        a.hid_out = (int *)c->r(c->hcur ? R_HID0 : R_HID1);
+        a.hxi_out = (double *)c->r(c->hcur ? R_HXI0 : R_HXI1);
+        a.hn_out = (int *)c->r(c->hcur ? R_HN0 : R_HN1);
+        a.last = s == c->p.n_sub - 1;
+        hipLaunchKernelGGL(k_dem, dim3(gb), dim3(128), 0, c->stream, a);
+        c->pcur ^= 1;
+        c->hcur ^= 1;
+    }
+    return hip_ok(c, hipGetLastError());
+}
+
+hipEvent_t take_event(pibm_ctx *c)
+{
+    if (!c->ev_free.empty()) {
+        hipEvent_t e = c->ev_free.back();
+        c->ev_free.pop_back();
+        return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    return e;
+}
+
+// Records an event pair around one phase when profiling is on.
+struct PhaseTimer {
+    pibm_ctx *c;
+    int phase;
+    hipEvent_t a = nullptr, b = nullptr;
+    PhaseTimer(pibm_ctx *ctx, int ph) : c(ctx), phase(ph) {
+        if (c->prof_on && (a = take_event(c)) && (b = take_event(c))) hipEventRecord(a, c->stream);
+    }
+    ~PhaseTimer() {
+        if (a && b) {
+            hipEventRecord(b, c->stream);
+            c->ev_rec[phase].emplace_back(a, b);
+        } else {
+            if (a) c->ev_free.push_back(a);
+            if (b) c->ev_free.push_back(b);
+        }
+    }
+};
+
+template <int DIM, class SF>
+int step_impl(pibm_ctx *c, int n)
+{
+    for (int s = 0; s < n; ++s) {
+        int st;
+        { PhaseTimer t(c, PIBM_PHASE_MARKERS); if ((st = launch_markers<DIM, SF>(c, true))) return st; }
+        { PhaseTimer t(c, PIBM_PHASE_BIN); if ((st = launch_bin(c))) return st; }
+        { PhaseTimer t(c, PIBM_PHASE_LATTICE); if ((st = launch_lbm<DIM, SF, false>(c))) return st; }
+        { PhaseTimer t(c, PIBM_PHASE_DEM); if ((st = launch_dem(c))) return st; }
+        c->cur ^= 1;
+        c->step++;
+    }
+    return PIBM_OK;
+}
+
+template <int DIM, class SF>
+int macro_impl(pibm_ctx *c)
+{
+    int st;
+    if ((st = launch_markers<DIM, SF>(c, false))) return st;
+    if ((st = launch_bin(c))) return st;
+    return launch_lbm<DIM, SF, true>(c);
+}
+
+template <template <int, class> class F, typename... A>
+int dispatch(pibm_ctx *c, A... args)
+{
+    const bool d3 = c->p.dim == 3;
+    switch (c->p.storage) {
+    case PIBM_STORE_F32: return d3 ? F<3, StF32>::run(c, args...) : F<2, StF32>::run(c, args...);
+    case PIBM_STORE_F64: return d3 ? F<3, StF64>::run(c, args...) : F<2, StF64>::run(c, args...);
+    case PIBM_STORE_F16DEV: return d3 ? F<3, StF16>::run(c, args...) : F<2, StF16>::run(c, args...);
+    default: return d3 ? F<3, StBF16>::run(c, args...) : F<2, StBF16>::run(c, args...);
+    }
+}
+
+template <int DIM, class SF> struct StepOp { static int run(pibm_ctx *c, int n) { return step_impl<DIM, SF>(c, n); } };
+template <int DIM, class SF> struct MacroOp { static int run(pibm_ctx *c) { return macro_impl<DIM, SF>(c); } };
+template <int DIM, class SF> struct InitOp {
+    static int run(pibm_ctx *c) {
+        using T = typename SF::T;
+        const int g = (int)std::min<long long>(4096, (c->P.N + 255) / 256);
+        hipLaunchKernelGGL((k_init<SF, Lat<DIM>::QG>), dim3(g), dim3(256), 0, c->stream, c->r(R_FA), c->r(R_GA),
+                           Lat<DIM>::Q, c->P.N, c->P.Ns, (T)(c->p.T_init - c->p.T_ref), Lat<DIM>::wg(0), Lat<DIM>::wg(1));
+        return hip_ok(c, hipGetLastError());
+    }
+};
+
+// ---- host conversions between absolute doubles and stored deviations ----
+float half_to_float(uint16_t h) { _Float16 v; std::memcpy(&v, &h, 2); return (float)v; }
+uint16_t float_to_half(float f) { _Float16 v = (_Float16)f; uint16_t h; std::memcpy(&h, &v, 2); return h; }
+float bf16_to_float(uint16_t h) { uint32_t u = (uint32_t)h << 16; float f; std::memcpy(&f, &u, 4); return f; }
+uint16_t float_to_bf16(float f)
+{
+    uint32_t u;
+    std::memcpy(&u, &f, 4);
+    if ((u & 0x7fffffffu) > 0x7f800000u) return (uint16_t)((u | 0x00400000u) >> 16);
+    u += 0x7fffu + ((u >> 16) & 1u);
+    return (uint16_t)(u >> 16);
+}
+
+double stored_to_dev(const pibm_ctx *c, const char *buf, size_t i, double w)
+{
+    switch (c->p.storage) {
+    case PIBM_STORE_F32: return ((const float *)buf)[i];
+    case PIBM_STORE_F64: return ((const double *)buf)[i];
+    case PIBM_STORE_F16DEV: return (double)(half_to_float(((const uint16_t *)buf)[i]) * (float)w);
+    default: return (double)(bf16_to_float(((const uint16_t *)buf)[i]) * (float)w);
+    }
+}
+
+void dev_to_stored(const pibm_ctx *c, char *buf, size_t i, double v, double w)
+{
+    switch (c->p.storage) {
+    case PIBM_STORE_F32: ((float *)buf)[i] = (float)v; break;
+    case PIBM_STORE_F64: ((double *)buf)[i] = v; break;
+    case PIBM_STORE_F16DEV: ((uint16_t *)buf)[i] = float_to_half((float)v * (float)(1.0 / w)); break;
+    default: ((uint16_t *)buf)[i] = float_to_bf16((float)v * (float)(1.0 / w)); break;
+    }
+}
+
+double wf(int dim, int q) { return dim == 2 ? Lat<2>::w(q) : Lat<3>::w(q); }
+double wgt(int dim, int q) { return dim == 2 ? Lat<2>::wg(q) : Lat<3>::wg(q); }
+
+DevParticle to_dev(const pibm_particle &q, int tmpl)
+{
+    DevParticle d{};
+    for (int k = 0; k < 3; ++k) { d.x[k] = q.x[k]; d.u[k] = q.u[k]; d.om[k] = q.omega[k]; d.th[k] = q.theta[k]; }
+    d.R = q.R; d.rho_r = q.rho_r; d.T = q.T; d.flags = q.flags; d.tmpl = tmpl;
+    return d;
+}
+
+int upload_particles(pibm_ctx *c, const pibm_particle *pt, int n)
+{
+    std::vector<DevParticle> dp(std::max(n, 1));
+    for (int i = 0; i < n; ++i) dp[i] = to_dev(pt[i], c->P.ptmpl[i]);
+    if (n == 0) return PIBM_OK;
+    hipError_t e = hipMemcpyAsync(c->r(c->pcur ? R_PART1 : R_PART0), dp.data(), sizeof(DevParticle) * n,
+                                  hipMemcpyHostToDevice, c->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    return hip_ok(c, e);
+}
+
+int status_from_err(int e)
+{
+    if (e & (ERR_CONTACTS | ERR_NEIGHBOURS)) return PIBM_ENOMEM;
+    if (e) return PIBM_EUNSTABLE;
+    return PIBM_OK;
+}
+
+int sync_impl(pibm_ctx *c)
+{
+    int e = 0;
+    hipError_t he = hipMemcpyAsync(&e, c->r(R_ERR), sizeof(int), hipMemcpyDeviceToHost, c->stream);
+    if (he == hipSuccess) he = hipStreamSynchronize(c->stream);
+    if (he != hipSuccess) return hip_ok(c, he);
+    if (e && !c->sticky) c->sticky = status_from_err(e);
+    return c->sticky;
+}
+
+}  // namespace
+
+// ============================================================================
+// C ABI
+// ============================================================================
+extern "C" {
+
+size_t pibm_workspace_bytes(const pibm_params *p, const pibm_particle *pt, int n)
+{
+    Plan P;
+    if (make_plan(p, pt, n, P) != PIBM_OK) return 0;
+    return P.off[R_COUNT];
+}
+
+int pibm_init(pibm_ctx **out, const pibm_params *p, const pibm_particle *pt, int n, void *ws, size_t ws_bytes,
+              void *stream)
+{
+    if (!out) return PIBM_EINVAL;
+    *out = nullptr;
+    pibm_ctx *c = new (std::nothrow) pibm_ctx();
+    if (!c) return PIBM_EINVAL;
+    int st = make_plan(p, pt, n, c->P);
+    if (st == PIBM_OK) st = check_particles(p, pt, n);
+    if (st == PIBM_OK && (!ws || ((uintptr_t)ws % ALIGN) != 0 || ws_bytes < c->P.off[R_COUNT])) st = PIBM_EINVAL;
+    if (st != PIBM_OK) { delete c; return st; }
+    c->p = *p;
+    c->d = derive(*p);
+    c->stream = (hipStream_t)stream;
+    c->ws = (char *)ws;
+    c->ws_bytes = ws_bytes;
+    c->cur = 0; c->pcur = 0; c->hcur = 0; c->step = 0; c->sticky = 0; c->device_lost = 0;
+    // templates, marker offsets
+    std::vector<double> tm((size_t)std::max(c->P.ntmpl_mk, 1LL) * 4, 0.0);
+    std::vector<int> ts(c->P.tmpls.size() + 1, 0);
+    std::vector<double> rext(c->P.tmpls.size() + 1, 0.0);
+    size_t k = 0;
+    for (size_t t = 0; t < c->P.tmpls.size(); ++t) {
+        ts[t] = (int)(k / 4);
+        std::copy(c->P.tmpls[t].off.begin(), c->P.tmpls[t].off.end(), tm.begin() + k);
+        k += c->P.tmpls[t].off.size();
+        rext[t] = p->marker_mode == PIBM_MARKERS_POINT ? 0.0 : c->P.tmpls[t].R;
+    }
+    ts[c->P.tmpls.size()] = (int)(k / 4);
+    hipError_t e = hipMemcpyAsync(c->r(R_TMPL), tm.data(), tm.size() * sizeof(double), hipMemcpyHostToDevice, c->stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(c->r(R_TMPL_START), ts.data(), ts.size() * sizeof(int), hipMemcpyHostToDevice, c->stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(c->r(R_TMPL_REXT), rext.data(), rext.size() * sizeof(double), hipMemcpyHostToDevice, c->stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(c->r(R_MK_START), c->P.mk_start.data(), c->P.mk_start.size() * sizeof(int), hipMemcpyHostToDevice, c->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    if (e != hipSuccess) { delete c; return PIBM_EDEVICE; }
+    // zeroed small state: tile starts (no particles => empty lists), history counts, error word
+    const int zero_regions[] = {R_TSTART, R_HN0, R_HN1, R_ERR, R_REACT};
+    for (int r : zero_regions) {
+        const size_t bytes = c->P.off[r + 1] - c->P.off[r];
+        hipLaunchKernelGGL(k_fill_int, dim3(std::max<size_t>(1, std::min<size_t>(1024, (bytes / 4 + 255) / 256))), dim3(256), 0,
+                           c->stream, (int *)c->r(r), (long long)(bytes / 4), 0);
+    }
+    st = dispatch<InitOp>(c);
+    if (st == PIBM_OK) st = upload_particles(c, pt, n);
+    if (st == PIBM_OK) st = hip_ok(c, hipStreamSynchronize(c->stream));
+    if (st != PIBM_OK) { delete c; return st; }
+    *out = c;
+    return PIBM_OK;
+}
+
+int pibm_step(pibm_ctx *c, int n)
+{
+    if (!c || n < 0) return PIBM_EINVAL;
+    if (c->device_lost) return PIBM_EDEVICE;
+    if (c->sticky) return c->sticky;         // the watchdog tripped: no further launches
+    return dispatch<StepOp>(c, n);
+}
+
+int pibm_sync(pibm_ctx *c)
+{
+    if (!c) return PIBM_EINVAL;
+    if (c->device_lost) return PIBM_EDEVICE;
+    return sync_impl(c);
+}
+
+int pibm_particles(pibm_ctx *c, pibm_particle *out, double *fth, int cap)
+{
+    if (!c || (!out && cap > 0) || cap < c->P.np) return PIBM_EINVAL;
+    if (c->device_lost) return PIBM_EDEVICE;
+    const int n = c->P.np;
+    std::vector<DevParticle> dp(std::max(n, 1));
+    std::vector<DevReact> dr(std::max(n, 1));
+    if (n) {
+        hipError_t e = hipMemcpyAsync(dp.data(), c->r(c->pcur ? R_PART1 : R_PART0), sizeof(DevParticle) * n,
+                                      hipMemcpyDeviceToHost, c->stream);
+        if (e == hipSuccess) e = hipMemcpyAsync(dr.data(), c->r(R_REACT), sizeof(DevReact) * n, hipMemcpyDeviceToHost, c->stream);
+        if (e != hipSuccess) return hip_ok(c, e);
+    }
+    const int st = sync_impl(c);
+    if (c->device_lost) return PIBM_EDEVICE;
+    for (int i = 0; i < n; ++i) {
+        pibm_particle &q = out[i];
+        for (int k = 0; k < 3; ++k) { q.x[k] = dp[i].x[k]; q.u[k] = dp[i].u[k]; q.omega[k] = dp[i].om[k]; q.theta[k] = dp[i].th[k]; }
+        q.R = dp[i].R; q.rho_r = dp[i].rho_r; q.T = dp[i].T; q.flags = dp[i].flags; q.reserved = 0;
+        if (fth) {
+            double *o = fth + 8 * (size_t)i;
+            for (int k = 0; k < 3; ++k) { o[k] = dr[i].F[k]; o[3 + k] = dr[i].tq[k]; }
+            o[6] = dr[i].H; o[7] = dr[i].dTA;
+        }
+    }
+    return st;
+}
+
+int pibm_set_particles(pibm_ctx *c, const pibm_particle *pt, int n)
+{
+    if (!c || n != c->P.np || (n && !pt)) return PIBM_EINVAL;
+    for (int i = 0; i < n; ++i)
+        if (pt[i].R != c->P.tmpls[c->P.ptmpl[i]].R) return PIBM_EINVAL;
+    int st = check_particles(&c->p, pt, n);
+    if (st) return st;
+    return upload_particles(c, pt, n);
+}
+
+int pibm_fields(pibm_ctx *c, double *rho, double *u, double *T)
+{
+    if (!c) return PIBM_EINVAL;
+    if (c->device_lost) return PIBM_EDEVICE;
+    int st = dispatch<MacroOp>(c);
+    if (st) return st;
+    const size_t ts = c->P.tsize, Ns = (size_t)c->P.Ns, N = (size_t)c->P.N;
+    std::vector<char> h(5 * Ns * ts);
+    hipError_t e = hipMemcpyAsync(h.data(), c->r(c->cur ? R_FA : R_FB), h.size(), hipMemcpyDeviceToHost, c->stream);
+    if (e != hipSuccess) return hip_ok(c, e);
+    st = sync_impl(c);
+    if (c->device_lost) return PIBM_EDEVICE;
+    auto get = [&](int k, size_t n) -> double {
+        return ts == 8 ? ((const double *)h.data())[k * Ns + n] : (double)((const float *)h.data())[k * Ns + n];
+    };
+    for (size_t n = 0; n < N; ++n) {
+        if (rho) rho[n] = get(0, n);
+        if (u) { u[3 * n] = get(1, n); u[3 * n + 1] = get(2, n); u[3 * n + 2] = get(3, n); }
+        if (T) T[n] = get(4, n);
+    }
+    return st;
+}
+
+int pibm_get_populations(pibm_ctx *c, double *f, double *g)
+{
+    if (!c || !f || !g) return PIBM_EINVAL;
+    if (c->device_lost) return PIBM_EDEVICE;
+    const int dim = c->p.dim, Q = c->P.Q, QG = c->P.QG;
+    const size_t Ns = (size_t)c->P.Ns, N = (size_t)c->P.N, ss = c->P.ssize;
+    std::vector<char> hf(Q * Ns * ss), hg(QG * Ns * ss);
+    hipError_t e = hipMemcpyAsync(hf.data(), c->r(c->cur ? R_FB : R_FA), hf.size(), hipMemcpyDeviceToHost, c->stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(hg.data(), c->r(c->cur ? R_GB : R_GA), hg.size(), hipMemcpyDeviceToHost, c->stream);
+    if (e != hipSuccess) return hip_ok(c, e);
+    const int st = sync_impl(c);
+    if (c->device_lost) return PIBM_EDEVICE;
+    for (int q = 0; q < Q; ++q)
+        for (size_t n = 0; n < N; ++n) f[q * N + n] = wf(dim, q) + stored_to_dev(c, hf.data(), q * Ns + n, wf(dim, q));
+    for (int q = 0; q < QG; ++q)
+        for (size_t n = 0; n < N; ++n)
+            g[q * N + n] = wgt(dim, q) * c->p.T_ref + stored_to_dev(c, hg.data(), q * Ns + n, wgt(dim, q));
+    return st;
+}
+
+int pibm_set_populations(pibm_ctx *c, const double *f, const double *g)
+{
+    if (!c || !f || !g) return PIBM_EINVAL;
+    if (c->device_lost) return PIBM_EDEVICE;
+    const int dim = c->p.dim, Q = c->P.Q, QG = c->P.QG;
+    const size_t Ns = (size_t)c->P.Ns, N = (size_t)c->P.N, ss = c->P.ssize;
+    std::vector<char> hf(Q * Ns * ss, 0), hg(QG * Ns * ss, 0);
+    for (int q = 0; q < Q; ++q)
+        for (size_t n = 0; n < N; ++n) dev_to_stored(c, hf.data(), q * Ns + n, f[q * N + n] - wf(dim, q), wf(dim, q));
+    for (int q = 0; q < QG; ++q)
+        for (size_t n = 0; n < N; ++n)
+            dev_to_stored(c, hg.data(), q * Ns + n, g[q * N + n] - wgt(dim, q) * c->p.T_ref, wgt(dim, q));
+    hipError_t e = hipMemcpyAsync(c->r(c->cur ? R_FB : R_FA), hf.data(), hf.size(), hipMemcpyHostToDevice, c->stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(c->r(c->cur ? R_GB : R_GA), hg.data(), hg.size(), hipMemcpyHostToDevice, c->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    return hip_ok(c, e);
+}
+
+long long pibm_num_nodes(const pibm_ctx *c) { return c ? c->P.N : 0; }
+long long pibm_num_markers(const pibm_ctx *c) { return c ? c->P.nmk : 0; }
+long long pibm_step_count(const pibm_ctx *c) { return c ? c->step : 0; }
+
+int pibm_derived(const pibm_ctx *c, double *out)
+{
+    if (!c || !out) return PIBM_EINVAL;
+    out[0] = c->d.tau_f; out[1] = c->d.tau_g; out[2] = c->d.gbeta; out[3] = c->d.nu; out[4] = c->d.alpha;
+    return PIBM_OK;
+}
+
+// ---- checkpoint blob: header, then raw device regions ----
+namespace {
+struct BlobHeader {
+    char magic[8];
+    int version;
+    int cur, pcur, hcur;
+    long long step;
+    pibm_params p;
+    long long N, np;
+};
+const int blob_regions[] = {R_FA, R_GA, R_FB, R_GB, R_PART0, R_PART1, R_REACT, R_HID0, R_HXI0, R_HN0, R_HID1, R_HXI1, R_HN1};
+}
+
+int pibm_save(pibm_ctx *c, void *buf, size_t cap, size_t *used)
+{
+    if (!c || !used) return PIBM_EINVAL;
+    size_t total = sizeof(BlobHeader);
+    for (int r : blob_regions) total += c->P.off[r + 1] - c->P.off[r];
+    *used = total;
+    if (!buf) return PIBM_OK;
+    if (cap < total) return PIBM_EINVAL;
+    BlobHeader h{};
+    std::memcpy(h.magic, "PIBMCKP", 8);
+    h.version = 1; h.cur = c->cur; h.pcur = c->pcur; h.hcur = c->hcur; h.step = c->step; h.p = c->p;
+    h.N = c->P.N; h.np = c->P.np;
+    std::memcpy(buf, &h, sizeof h);
+    char *o = (char *)buf + sizeof h;
+    for (int r : blob_regions) {
+        const size_t b = c->P.off[r + 1] - c->P.off[r];
+        hipError_t e = hipMemcpyAsync(o, c->r(r), b, hipMemcpyDeviceToHost, c->stream);
+        if (e != hipSuccess) return hip_ok(c, e);
+        o += b;
+    }
+    return hip_ok(c, hipStreamSynchronize(c->stream));
+}
+
+int pibm_load(pibm_ctx *c, const void *buf, size_t n)
+{
+    if (!c || !buf || n < sizeof(BlobHeader)) return PIBM_EINVAL;
+    BlobHeader h;
+    std::memcpy(&h, buf, sizeof h);
+    if (std::memcmp(h.magic, "PIBMCKP", 8) != 0 || h.version != 1) return PIBM_ESTATE;
+    if (std::memcmp(&h.p, &c->p, sizeof(pibm_params)) != 0 || h.N != c->P.N || h.np != c->P.np) return PIBM_ESTATE;
+    size_t total = sizeof(BlobHeader);
+    for (int r : blob_regions) total += c->P.off[r + 1] - c->P.off[r];
+    if (n < total) return PIBM_EINVAL;
+    const char *o = (const char *)buf + sizeof h;
+    for (int r : blob_regions) {
+        const size_t b = c->P.off[r + 1] - c->P.off[r];
+        hipError_t e = hipMemcpyAsync(c->r(r), o, b, hipMemcpyHostToDevice, c->stream);
+        if (e != hipSuccess) return hip_ok(c, e);
+        o += b;
+    }
+    c->cur = h.cur; c->pcur = h.pcur; c->hcur = h.hcur; c->step = h.step;
+    return hip_ok(c, hipStreamSynchronize(c->stream));
+}
+
+int pibm_profile(pibm_ctx *c, int enable)
+{
+    if (!c) return PIBM_EINVAL;
+    c->prof_on = enable ? 1 : 0;
+    return PIBM_OK;
+}
+
+int pibm_profile_read(pibm_ctx *c, double *ms, long long *count)
+{
+    if (!c || !ms || !count) return PIBM_EINVAL;
+    if (c->device_lost) return PIBM_EDEVICE;
+    hipError_t e = hipStreamSynchronize(c->stream);
+    if (e != hipSuccess) return hip_ok(c, e);
+    for (int ph = 0; ph < PIBM_NPHASE; ++ph) {
+        double acc = 0.0;
+        for (auto &pr : c->ev_rec[ph]) {
+            float t = 0.0f;
+            if (hipEventElapsedTime(&t, pr.first, pr.second) == hipSuccess) acc += t;
+            c->ev_free.push_back(pr.first);
+            c->ev_free.push_back(pr.second);
+        }
+        ms[ph] = acc;
+        count[ph] = (long long)c->ev_rec[ph].size();
+        c->ev_rec[ph].clear();
+    }
+    return PIBM_OK;
+}
+
+int pibm_destroy(pibm_ctx *c)
+{
+    if (!c) return PIBM_OK;
+    for (int ph = 0; ph < PIBM_NPHASE; ++ph)
+        for (auto &pr : c->ev_rec[ph]) c->ev_free.insert(c->ev_free.end(), {pr.first, pr.second});
+    for (hipEvent_t e : c->ev_free) hipEventDestroy(e);
+    delete c;
+    return PIBM_OK;
+}
+
+const char *pibm_strerror(int s)
+{
+    switch (s) {
+    case PIBM_OK: return "ok";
+    case PIBM_EINVAL: return "invalid argument (parameters, sizes, pointers or workspace)";
+    case PIBM_ENOMEM: return "device capacity exceeded (contact slots or neighbour list)";
+    case PIBM_EDEVICE: return "HIP runtime error";
+    case PIBM_EUNSTABLE: return "watchdog: NaN or |u| > 0.4, stale neighbour list, or particle outside the domain";
+    case PIBM_EOVERLAP: return "initial particles overlap";
+    case PIBM_ESTATE: return "checkpoint does not match this context";
+    default: return "unknown status";
+    }
+}
+
+}  // extern "C"

@@ -1,0 +1,1054 @@
+// pibm_device.h -- gfx950 kernels of the coupled thermal LBM-PIBM-DEM step.
+//
+// Zhang, Yuan, Trias, Yu, Tan & Oliva, arXiv 1502.01159:
+//   Sec. 2.1  BGK for f (Eq. lbm2) and g (Eq. lbm2.5), equilibria (lbm3,
+//             lbm3.5), macroscopic moments with half-force / half-source;
+//   Sec. 2.2  PIBM: Lagrange interpolation (lbm5-lbm6), point exchange
+//             (lbm7, lbm7.5, lbm8), Guo forcing (lbm9), spreading with the
+//             cosine kernel (lbm10-lbm12), heat source (lbm12.5, lbm12.6),
+//             reaction on the particle (lbm13);
+//   Sec. 2.3  DEM: Newton-Euler (demgov), Hertz normal and
+//             Mindlin-Deresiewicz tangential contact.
+//
+// Data layout in HBM: structure of arrays, population q of node n at
+// q * Ns + n, n = (k * ny + j) * nx + i (x fastest), two copies (A read,
+// B written) swapped every step.  Populations are stored as deviations from
+// the rest state, f - w (rho0 = 1) and g - w T_ref; 16-bit storage keeps the
+// deviation divided by w so that every direction uses the same range.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <hip/hip_fp16.h>
+#include <stdint.h>
+
+namespace pibm {
+
+// --------------------------------------------------------------------------
+// Lattices.  Flow: D2Q9 / D3Q19 BGK.  Temperature: D2Q5 / D3Q7 with a linear
+// equilibrium, c_sg^2 = 1/3 (D2Q5) and 1/4 (D3Q7).
+// --------------------------------------------------------------------------
+template <int DIM> struct Lat;
+
+template <> struct Lat<2> {
+    static constexpr int Q = 9, QG = 5;
+    __host__ __device__ static constexpr int e(int q, int d) {
+        // rest, +x, +y, -x, -y, (+x+y), (-x+y), (-x-y), (+x-y)
+        return d == 2 ? 0
+             : d == 0 ? (q == 1 || q == 5 || q == 8 ? 1 : (q == 3 || q == 6 || q == 7 ? -1 : 0))
+                      : (q == 2 || q == 5 || q == 6 ? 1 : (q == 4 || q == 7 || q == 8 ? -1 : 0));
+    }
+    __host__ __device__ static constexpr int opp(int q) {
+        return q == 0 ? 0 : q == 1 ? 3 : q == 2 ? 4 : q == 3 ? 1 : q == 4 ? 2 : q == 5 ? 7 : q == 6 ? 8 : q == 7 ? 5 : 6;
+    }
+    __host__ __device__ static constexpr double w(int q) { return q == 0 ? 4.0 / 9.0 : (q < 5 ? 1.0 / 9.0 : 1.0 / 36.0); }
+    __host__ __device__ static constexpr double wg(int q) { return q == 0 ? 1.0 / 3.0 : 1.0 / 6.0; }
+    static constexpr double csg2_inv = 3.0;
+};
+
+template <> struct Lat<3> {
+    static constexpr int Q = 19, QG = 7;
+    // rest; +-x, +-y, +-z; then the 12 edge directions in opposite pairs
+    __host__ __device__ static constexpr int e(int q, int d) {
+        return d == 0 ? (q == 1 || q == 7 || q == 9 || q == 11 || q == 13 ? 1
+                         : (q == 2 || q == 8 || q == 10 || q == 12 || q == 14 ? -1 : 0))
+             : d == 1 ? (q == 3 || q == 7 || q == 10 || q == 15 || q == 17 ? 1
+                         : (q == 4 || q == 8 || q == 9 || q == 16 || q == 18 ? -1 : 0))
+                      : (q == 5 || q == 11 || q == 14 || q == 15 || q == 18 ? 1
+                         : (q == 6 || q == 12 || q == 13 || q == 16 || q == 17 ? -1 : 0));
+    }
+    __host__ __device__ static constexpr int opp(int q) { return q == 0 ? 0 : ((q & 1) ? q + 1 : q - 1); }
+    __host__ __device__ static constexpr double w(int q) { return q == 0 ? 1.0 / 3.0 : (q < 7 ? 1.0 / 18.0 : 1.0 / 36.0); }
+    __host__ __device__ static constexpr double wg(int q) { return q == 0 ? 0.25 : 0.125; }
+    static constexpr double csg2_inv = 4.0;
+};
+
+// --------------------------------------------------------------------------
+// Counter-based uniform numbers for stochastic rounding: a 32-bit integer
+// hash (xorshift-multiply finaliser) of (node, population, step).
+// --------------------------------------------------------------------------
+__host__ __device__ __forceinline__ uint32_t mix32(uint32_t x)
+{
+    x ^= x >> 16; x *= 0x7feb352du;
+    x ^= x >> 15; x *= 0x846ca68bu;
+    x ^= x >> 16;
+    return x;
+}
+__device__ __forceinline__ float unit_hash(uint32_t n, uint32_t q, uint32_t step)
+{
+    const uint32_t h = mix32(n * 0x9e3779b1u ^ mix32(q * 0x85ebca77u + step * 0xc2b2ae3du));
+    return (float)(h >> 8) * (1.0f / 16777216.0f);
+}
+
+// --------------------------------------------------------------------------
+// Storage traits: load a stored deviation as the compute type; store
+// old + increment.  FP32 and the 16-bit formats round the store
+// stochastically (up or down with probability set by the residual, from the
+// hash above), so that increments smaller than half an ulp of a slowly
+// changing population are kept on average instead of being discarded every
+// step; the hash makes it reproducible bit for bit.  `w` is the lattice
+// weight of the direction (16-bit formats store dev / w).
+// --------------------------------------------------------------------------
+struct StF32 {
+    using S = float; using T = float; using C = double;
+    static __device__ __forceinline__ T ld(const S *p, size_t i, double) { return p[i]; }
+    static __device__ __forceinline__ void st(S *p, size_t i, T v, double) { p[i] = v; }
+    template <class A, class I>
+    static __device__ __forceinline__ void st_sum(S *p, size_t i, A old, I inc, double, float u)
+    {
+        const double s = (double)old + (double)inc;            // exact for float operands
+        float r = (float)s;
+        const double e = s - (double)r;                        // exact residual, |e| <= ulp/2
+        if (e != 0.0) {
+            const float r2 = nextafterf(r, e > 0.0 ? INFINITY : -INFINITY);
+            if ((double)u * fabs((double)r2 - (double)r) < fabs(e)) r = r2;
+        }
+        p[i] = r;
+    }
+};
+struct StF64 {
+    using S = double; using T = double; using C = double;
+    static __device__ __forceinline__ T ld(const S *p, size_t i, double) { return p[i]; }
+    static __device__ __forceinline__ void st(S *p, size_t i, T v, double) { p[i] = v; }
+    template <class A, class I>
+    static __device__ __forceinline__ void st_sum(S *p, size_t i, A old, I inc, double, float) { p[i] = (T)(old + inc); }
+};
+// Stochastic rounding of a float `s` to a 16-bit format whose value of a bit
+// pattern is dec(bits); `h` is the round-to-nearest pattern of s.  The
+// neighbour on the other side of s is taken with probability |s - dec(h)| /
+// |dec(h') - dec(h)|.
+template <class Dec>
+__device__ __forceinline__ uint16_t sr16(float s, uint16_t h, float u, Dec dec)
+{
+    const float v = dec(h);
+    const float e = s - v;
+    if (!(e != 0.0f) || !(fabsf(s) < 3.0e38f)) return h;
+    const bool up = e > 0.0f;                       // neighbour toward +inf ?
+    uint16_t h2;
+    if ((h & 0x7fffu) == 0) h2 = up ? 0x0001u : 0x8001u;
+    else if (!(h & 0x8000u)) h2 = up ? (uint16_t)(h + 1) : (uint16_t)(h - 1);
+    else h2 = up ? (uint16_t)(h - 1) : (uint16_t)(h + 1);
+    const float gap = fabsf(dec(h2) - v);
+    return (u * gap < fabsf(e)) ? h2 : h;
+}
+
+struct StF16 {
+    using S = __half; using T = float; using C = float;
+    static __device__ __forceinline__ float dec(uint16_t b) { __half h; __builtin_memcpy(&h, &b, 2); return __half2float(h); }
+    static __device__ __forceinline__ uint16_t enc(float v) { __half h = __float2half_rn(v); uint16_t b; __builtin_memcpy(&b, &h, 2); return b; }
+    static __device__ __forceinline__ T ld(const S *p, size_t i, double w) { return __half2float(p[i]) * (float)w; }
+    static __device__ __forceinline__ void st(S *p, size_t i, T v, double w) { p[i] = __float2half_rn(v * (float)(1.0 / w)); }
+    template <class A, class I>
+    static __device__ __forceinline__ void st_sum(S *p, size_t i, A old, I inc, double w, float u)
+    {
+        const float s = (float)(old + inc) * (float)(1.0 / w);
+        const uint16_t b = sr16(s, enc(s), u, dec);
+        __half h;
+        __builtin_memcpy(&h, &b, 2);
+        p[i] = h;
+    }
+};
+struct StBF16 {
+    using S = uint16_t; using T = float; using C = float;
+    static __device__ __forceinline__ T ld(const S *p, size_t i, double w) {
+        return __uint_as_float(((uint32_t)p[i]) << 16) * (float)w;
+    }
+    static __device__ __forceinline__ void st(S *p, size_t i, T v, double w) {
+        float s = v * (float)(1.0 / w);
+        uint32_t u = __float_as_uint(s);
+        // round to nearest even; NaN stays NaN
+        uint32_t r = (u & 0x7fffffffu) > 0x7f800000u ? (u | 0x00400000u) : u + 0x7fffu + ((u >> 16) & 1u);
+        p[i] = (uint16_t)(r >> 16);
+    }
+    static __device__ __forceinline__ float dec(uint16_t b) { return __uint_as_float(((uint32_t)b) << 16); }
+    template <class A, class I>
+    static __device__ __forceinline__ void st_sum(S *p, size_t i, A old, I inc, double w, float u)
+    {
+        const float s = (float)(old + inc) * (float)(1.0 / w);
+        uint32_t x = __float_as_uint(s);
+        const uint32_t r = (x & 0x7fffffffu) > 0x7f800000u ? (x | 0x00400000u) : x + 0x7fffu + ((x >> 16) & 1u);
+        p[i] = sr16(s, (uint16_t)(r >> 16), u, dec);
+    }
+};
+
+// --------------------------------------------------------------------------
+// Shared records.
+// --------------------------------------------------------------------------
+struct DevParticle {               // 128 bytes, FP64
+    double x[3], u[3], om[3], th[3];
+    double R, rho_r, T;
+    int flags, tmpl;
+};
+struct DevReact {                  // per-particle reactions of the last step
+    double F[3], tq[3], H, dTA;
+};
+template <typename T> struct alignas(16) MarkerRec {
+    int b[3];                      // floor(X_l) per axis (unwrapped)
+    int pad;
+    T t[3];                        // X_l - floor(X_l)
+    T fa[3];                       // F_l A_l (force density times weight)
+    T qa;                          // Q_l A_l
+};
+
+enum : int {
+    ERR_FIELD = 1,        // NaN / out-of-range rho or |u|
+    ERR_CONTACTS = 2,     // contact slots exhausted
+    ERR_NEIGHBOURS = 4,   // neighbour list full
+    ERR_STALE = 8,        // a particle moved more than skin/2 since the list was built
+    ERR_DOMAIN = 16,      // particle centre outside the walls / NaN state
+};
+
+// Once the watchdog word is set the state is no longer meaningful; every
+// kernel of the following steps returns at entry (the host reports the error
+// at its next synchronisation).  Kernels with barriers take the decision once
+// per workgroup so that all of its threads agree.
+__device__ __forceinline__ bool halted(const int *err) { return __atomic_load_n(err, __ATOMIC_RELAXED) != 0; }
+
+__device__ __forceinline__ bool block_halted(const int *err)
+{
+    __shared__ int s_halt;
+    if (threadIdx.x == 0) s_halt = halted(err) ? 1 : 0;
+    __syncthreads();
+    return s_halt != 0;
+}
+
+constexpr int TILE_X = 64;
+template <int DIM> struct Tile {
+    static constexpr int X = TILE_X, Y = DIM == 3 ? 4 : 16, Z = DIM == 3 ? 4 : 1;
+    static constexpr int N = X * Y * Z;           // 1024 nodes, 4 per thread
+};
+constexpr int LBM_THREADS = 256;
+constexpr double FIX_SCALE = 281474976710656.0;       // 2^48
+constexpr double FIX_INV = 1.0 / 281474976710656.0;
+
+template <typename T> struct LbmArgs {
+    int nx, ny, nz;
+    int per[3];
+    long long Ns;                  // stride between population arrays (elements)
+    int ntx, nty, ntz, ntiles;
+    double omf, omg;               // 1 / tau
+    double gf, gg;                 // 1 - 1 / (2 tau)
+    double gbeta;
+    double Tref;
+    double tw[6];                  // T_wall - T_ref per face
+    const void *fA, *gA;
+    void *fB, *gB;
+    const int *tile_start, *tile_items;
+    const int *mk_start;
+    const MarkerRec<T> *mk;
+    int *err;
+    T *macro;                      // macro pass: rho, u[3], T at k * Ns + n
+    uint32_t step;                 // step counter (stochastic-rounding stream)
+};
+
+// --------------------------------------------------------------------------
+// Neighbour coordinates of a node (wrap on periodic axes, invalid at walls).
+// --------------------------------------------------------------------------
+struct Nbr {
+    int m[3], p[3];                // coordinate - 1, + 1
+    bool vm[3], vp[3];
+};
+
+__device__ __forceinline__ void nbr_axis(int c, int n, int per, int &m, int &p, bool &vm, bool &vp)
+{
+    m = c - 1; p = c + 1; vm = true; vp = true;
+    if (c == 0) { if (per) m = n - 1; else vm = false; }
+    if (c == n - 1) { if (per) p = 0; else vp = false; }
+}
+
+// Pull streaming (Eqs. lbm2, lbm2.5 read at the arrival node): deviation
+// populations of node (x, y, z) after streaming, with halfway bounce-back for
+// f and anti-bounce-back (Dirichlet wall temperature) for g.
+template <int DIM, class SF, class T, class TG>
+__device__ __forceinline__ void pull(const LbmArgs<T> &a, int x, int y, int z, T *f, TG *g)
+{
+    using L = Lat<DIM>;
+    using S = typename SF::S;
+    const S *fa = (const S *)a.fA;
+    const S *ga = (const S *)a.gA;
+    Nbr nb;
+    nbr_axis(x, a.nx, a.per[0], nb.m[0], nb.p[0], nb.vm[0], nb.vp[0]);
+    nbr_axis(y, a.ny, a.per[1], nb.m[1], nb.p[1], nb.vm[1], nb.vp[1]);
+    if (DIM == 3) nbr_axis(z, a.nz, a.per[2], nb.m[2], nb.p[2], nb.vm[2], nb.vp[2]);
+    else { nb.m[2] = nb.p[2] = 0; nb.vm[2] = nb.vp[2] = true; }
+    const int c[3] = {x, y, z};
+    const size_t sxy = (size_t)a.nx * a.ny;
+    const size_t self = (size_t)z * sxy + (size_t)y * a.nx + x;
+#pragma unroll
+    for (int q = 0; q < L::Q; ++q) {
+        int s[3];
+        bool v = true;
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+            const int e = L::e(q, d);
+            s[d] = e > 0 ? nb.m[d] : (e < 0 ? nb.p[d] : c[d]);
+            v = v && (e > 0 ? nb.vm[d] : (e < 0 ? nb.vp[d] : true));
+        }
+        if (v) f[q] = SF::ld(fa + (size_t)q * a.Ns, (size_t)s[2] * sxy + (size_t)s[1] * a.nx + s[0], L::w(q));
+        else f[q] = SF::ld(fa + (size_t)L::opp(q) * a.Ns, self, L::w(q));
+    }
+#pragma unroll
+    for (int q = 0; q < L::QG; ++q) {
+        int s[3];
+        bool v = true;
+        int face = 0;
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+            const int e = L::e(q, d);
+            s[d] = e > 0 ? nb.m[d] : (e < 0 ? nb.p[d] : c[d]);
+            const bool ok = e > 0 ? nb.vm[d] : (e < 0 ? nb.vp[d] : true);
+            if (e != 0) face = 2 * d + (e > 0 ? 0 : 1);
+            v = v && ok;
+        }
+        if (v) g[q] = (TG)SF::ld(ga + (size_t)q * a.Ns, (size_t)s[2] * sxy + (size_t)s[1] * a.nx + s[0], L::wg(q));
+        else g[q] = -(TG)SF::ld(ga + (size_t)L::opp(q) * a.Ns, self, L::wg(q)) + (TG)(2.0 * L::wg(q) * a.tw[face]);
+    }
+}
+
+// Raw moments of the streamed deviations: rho - 1, j, S - T_ref.
+template <int DIM, class C, class T>
+__device__ __forceinline__ void moments(const T *f, const C *g, C &drho, C *j, C &dS)
+{
+    using L = Lat<DIM>;
+    drho = 0; j[0] = 0; j[1] = 0; j[2] = 0; dS = 0;
+#pragma unroll
+    for (int q = 0; q < L::Q; ++q) {
+        drho += f[q];
+#pragma unroll
+        for (int d = 0; d < DIM; ++d) {
+            if (L::e(q, d) > 0) j[d] += f[q];
+            else if (L::e(q, d) < 0) j[d] -= f[q];
+        }
+    }
+#pragma unroll
+    for (int q = 0; q < L::QG; ++q) dS += g[q];
+}
+
+// --------------------------------------------------------------------------
+// Cosine kernel weights of Eq. (lbm12) for the four nodes b-1 .. b+2 around a
+// point at b + t, 0 <= t < 1: with c = cos(pi t / 2), s = sin(pi t / 2),
+//   delta(-1-t) = (1 - s)/4, delta(-t) = (1 + c)/4,
+//   delta(1-t)  = (1 + s)/4, delta(2-t) = (1 - c)/4.
+// --------------------------------------------------------------------------
+__device__ __forceinline__ void cos_weights(float t, float *w)
+{
+    float s, c;
+    sincospif(0.5f * t, &s, &c);
+    w[0] = 0.25f * (1.0f - s); w[1] = 0.25f * (1.0f + c); w[2] = 0.25f * (1.0f + s); w[3] = 0.25f * (1.0f - c);
+}
+__device__ __forceinline__ void cos_weights(double t, double *w)
+{
+    double s, c;
+    sincospi(0.5 * t, &s, &c);
+    w[0] = 0.25 * (1.0 - s); w[1] = 0.25 * (1.0 + c); w[2] = 0.25 * (1.0 + s); w[3] = 0.25 * (1.0 - c);
+}
+
+__device__ __forceinline__ int wrap_or_out(int c, int n, int per)
+{
+    if (per) { c %= n; if (c < 0) c += n; return c; }
+    return (c < 0 || c >= n) ? -1 : c;
+}
+
+__device__ __forceinline__ unsigned long long to_fix(double v)
+{
+    return (unsigned long long)__double2ll_rn(v * FIX_SCALE);
+}
+
+// --------------------------------------------------------------------------
+// K1: fused pull-stream + moments + PIBM spreading (Eqs. lbm10-lbm12,
+// lbm12.6) + buoyancy + Guo-forced BGK for f (lbm2, lbm3, lbm9) and
+// source-forced BGK for g (lbm2.5, lbm12.5).  One workgroup per 1024-node
+// tile; the tile's spread force and heat are accumulated in LDS as 2^-48
+// fixed point (order-independent, hence bitwise reproducible) and never
+// written to HBM.
+// --------------------------------------------------------------------------
+template <int DIM, class SF, bool MACRO>
+__global__ __launch_bounds__(LBM_THREADS) void k_lbm(LbmArgs<typename SF::T> a)
+{
+    using T = typename SF::T;
+    using L = Lat<DIM>;
+    using TL = Tile<DIM>;
+    constexpr int NC = DIM + 1;
+    __shared__ unsigned long long acc[NC * TL::N];
+
+    // XCD-aware order: consecutive workgroups go to different XCDs; give each
+    // XCD a contiguous run of tiles so that neighbours share an L2.
+    const int G = gridDim.x, b = blockIdx.x;
+    const int q8 = G >> 3, r8 = G & 7, xcd = b & 7, slot = b >> 3;
+    const int t = xcd * q8 + (xcd < r8 ? xcd : r8) + slot;
+    const int tx = t % a.ntx, rem = t / a.ntx, ty = rem % a.nty, tz = rem / a.nty;
+    const int x0 = tx * TL::X, y0 = ty * TL::Y, z0 = tz * TL::Z;
+    const int tid = threadIdx.x;
+    if (block_halted(a.err)) return;
+
+    const int ps = a.tile_start[t], pe = a.tile_start[t + 1];
+    const bool has = pe > ps;
+    if (has) {
+        for (int i = tid; i < NC * TL::N; i += LBM_THREADS) acc[i] = 0ull;
+        __syncthreads();
+        const int org[3] = {x0, y0, z0};
+        const int ext[3] = {TL::X, TL::Y, TL::Z};
+        const int nn[3] = {a.nx, a.ny, a.nz};
+        for (int e = ps; e < pe; ++e) {
+            const int p = a.tile_items[e];
+            const int m1 = a.mk_start[p + 1];
+            for (int m = a.mk_start[p] + tid; m < m1; m += LBM_THREADS) {
+                const MarkerRec<T> r = a.mk[m];
+                int loc[3][4];
+                double wt[3][4];
+                bool any = true;
+#pragma unroll
+                for (int d = 0; d < 3; ++d) {
+                    if (d >= DIM) {
+                        loc[d][0] = 0; loc[d][1] = loc[d][2] = loc[d][3] = -1;
+                        wt[d][0] = 1; wt[d][1] = wt[d][2] = wt[d][3] = 0;
+                        continue;
+                    }
+                    bool hit = false;
+#pragma unroll
+                    for (int k = 0; k < 4; ++k) {
+                        const int gc = wrap_or_out(r.b[d] - 1 + k, nn[d], a.per[d]);
+                        const int l = gc - org[d];
+                        loc[d][k] = (gc >= 0 && l >= 0 && l < ext[d]) ? l : -1;
+                        hit = hit || loc[d][k] >= 0;
+                    }
+                    any = any && hit;
+                }
+                if (!any) continue;
+#pragma unroll
+                for (int d = 0; d < DIM; ++d) cos_weights((double)r.t[d], wt[d]);
+#pragma unroll
+                for (int kz = 0; kz < (DIM == 3 ? 4 : 1); ++kz) {
+                    if (loc[2][kz] < 0) continue;
+#pragma unroll
+                    for (int ky = 0; ky < 4; ++ky) {
+                        if (loc[1][ky] < 0) continue;
+#pragma unroll
+                        for (int kx = 0; kx < 4; ++kx) {
+                            if (loc[0][kx] < 0) continue;
+                            const int idx = loc[0][kx] + TL::X * (loc[1][ky] + TL::Y * loc[2][kz]);
+                            const double W = wt[0][kx] * wt[1][ky] * wt[2][kz];
+#pragma unroll
+                            for (int c = 0; c < DIM; ++c) atomicAdd(&acc[c * TL::N + idx], to_fix((double)r.fa[c] * W));
+                            atomicAdd(&acc[DIM * TL::N + idx], to_fix((double)r.qa * W));
+                        }
+                    }
+                }
+            }
+        }
+        __syncthreads();
+    }
+
+    const size_t sxy = (size_t)a.nx * a.ny;
+    bool bad = false;
+#pragma unroll 1
+    for (int kk = 0; kk < TL::N / LBM_THREADS; ++kk) {
+        const int ln = tid + LBM_THREADS * kk;
+        const int lx = ln % TL::X, lr = ln / TL::X, ly = lr % TL::Y, lz = lr / TL::Y;
+        const int x = x0 + lx, y = y0 + ly, z = z0 + lz;
+        if (x >= a.nx || y >= a.ny || z >= a.nz) continue;
+        // Populations stay in registers at storage precision; moments and the
+        // collision are formed in the compute type C (FP64 for FP32 storage:
+        // in a slowly changing region FP32 arithmetic rounds the same way
+        // every step and drifts by ~steps x ulp).
+        using C = typename SF::C;
+        C FB[3] = {0, 0, 0};
+        C QB = 0;
+        if (has) {
+#pragma unroll
+            for (int c = 0; c < DIM; ++c) FB[c] = (C)((double)(long long)acc[c * TL::N + ln] * FIX_INV);
+            QB = (C)((double)(long long)acc[DIM * TL::N + ln] * FIX_INV);
+        }
+        T f[L::Q];
+        C g[L::QG];
+        pull<DIM, SF, T, C>(a, x, y, z, f, g);
+        C drho, j[3], dS;
+        moments<DIM, C>(f, g, drho, j, dS);
+        // Sec. 2.1 after Eq. (lbm3.5): T = S + Q_B / 2, u = (j + F / 2) / rho with
+        // F = F_B + g beta (T - T_ref) e_up (buoyancy along +y in 2D, +z in 3D).
+        const C rho = (C)1 + drho;
+        const C dT = dS + (C)0.5 * QB;
+        C F[3] = {FB[0], FB[1], FB[2]};
+        F[DIM - 1] += (C)a.gbeta * dT;
+        const C inv = (C)1 / rho;
+        C u[3] = {0, 0, 0};
+#pragma unroll
+        for (int d = 0; d < DIM; ++d) u[d] = (j[d] + (C)0.5 * F[d]) * inv;
+        const C uu = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
+        bad = bad || !(uu <= (C)0.16) || !(rho > (C)0.5 && rho < (C)2);
+        const size_t n = (size_t)z * sxy + (size_t)y * a.nx + x;
+        if (MACRO) {
+            a.macro[n] = (T)rho;
+            a.macro[a.Ns + n] = (T)u[0];
+            a.macro[2 * a.Ns + n] = (T)u[1];
+            a.macro[3 * a.Ns + n] = (T)u[2];
+            a.macro[4 * a.Ns + n] = (T)(a.Tref + (double)dT);
+            continue;
+        }
+        const C uF = u[0] * F[0] + u[1] * F[1] + u[2] * F[2];
+        typename SF::S *fb = (typename SF::S *)a.fB;
+        typename SF::S *gb = (typename SF::S *)a.gB;
+        const C omf = (C)a.omf, gf = (C)a.gf, omg = (C)a.omg, gg = (C)a.gg;
+#pragma unroll
+        for (int q = 0; q < L::Q; ++q) {
+            C eu = 0, eF = 0;
+#pragma unroll
+            for (int d = 0; d < DIM; ++d) {
+                if (L::e(q, d) > 0) { eu += u[d]; eF += F[d]; }
+                else if (L::e(q, d) < 0) { eu -= u[d]; eF -= F[d]; }
+            }
+            const C wq = (C)L::w(q);
+            // f^eq - w (Eq. lbm3) and the Guo source (Eq. lbm9)
+            const C feq = wq * (drho + rho * ((C)3 * eu + (C)4.5 * eu * eu - (C)1.5 * uu));
+            const C src = gf * wq * ((C)3 * (eF - uF) + (C)9 * eu * eF);
+            const C fq = (C)f[q];
+            SF::st_sum(fb + (size_t)q * a.Ns, n, f[q], src - omf * (fq - feq), L::w(q),
+                       unit_hash((uint32_t)n, (uint32_t)q, a.step));
+        }
+        const C Tabs = (C)a.Tref + dT;
+#pragma unroll
+        for (int q = 0; q < L::QG; ++q) {
+            C eu = 0;
+#pragma unroll
+            for (int d = 0; d < DIM; ++d) {
+                if (L::e(q, d) > 0) eu += u[d];
+                else if (L::e(q, d) < 0) eu -= u[d];
+            }
+            const C wq = (C)L::wg(q);
+            // g^eq - w T_ref (linear thermal equilibrium) and the heat source (Eq. lbm12.5)
+            const C geq = wq * (dT + Tabs * eu * (C)L::csg2_inv);
+            SF::st_sum(gb + (size_t)q * a.Ns, n, g[q], gg * wq * QB - omg * (g[q] - geq), L::wg(q),
+                       unit_hash((uint32_t)n, (uint32_t)(32 + q), a.step));
+        }
+    }
+    if (bad) atomicOr(a.err, ERR_FIELD);
+}
+
+// --------------------------------------------------------------------------
+// K2: Lagrangian points of one particle per workgroup.  Generates
+// X_l = X_p + r_l and U_l = U_p + Omega x r_l, interpolates the streamed
+// moments with the i_max = 2 Lagrange polynomial (Eq. lbm6: multilinear on
+// the cell corners, indices clamped at walls / wrapped on periodic axes),
+// forms the exchange F_l = 2 (rho_l U_l - j_l) and Q_l = 2 kappa (T_p - T_l)
+// (Eqs. lbm7, lbm7.5, lbm8 summed over the bounced directions), writes the
+// marker records that K1 spreads, and reduces the reactions of Eq. (lbm13)
+// in FP64 in a fixed order.
+// --------------------------------------------------------------------------
+template <typename T> struct MkArgs {
+    LbmArgs<T> lb;
+    const DevParticle *part;
+    const double4 *tmpl;           // r_l (x, y, z) and A_l
+    const int *tmpl_start;
+    const int *mk_start;
+    MarkerRec<T> *mk;
+    DevReact *react;               // NULL in the macro pass
+    double kappa, Tref;
+};
+
+__device__ __forceinline__ int clamp_or_wrap(int c, int n, int per)
+{
+    if (per) { c %= n; if (c < 0) c += n; return c; }
+    return c < 0 ? 0 : (c >= n ? n - 1 : c);
+}
+
+template <int DIM, class SF>
+__global__ __launch_bounds__(256) void k_markers(MkArgs<typename SF::T> a)
+{
+    using T = typename SF::T;
+    using L = Lat<DIM>;
+    __shared__ double red[8][256];
+    const int p = blockIdx.x, tid = threadIdx.x;
+    if (block_halted(a.lb.err)) return;
+    const DevParticle P = a.part[p];
+    const int m0 = a.mk_start[p], nm = a.mk_start[p + 1] - m0;
+    const int t0 = a.tmpl_start[P.tmpl];
+    const int nn[3] = {a.lb.nx, a.lb.ny, a.lb.nz};
+    double s[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    for (int m = tid; m < nm; m += 256) {
+        const double4 r4 = a.tmpl[t0 + m];
+        const double r[3] = {r4.x, r4.y, DIM == 3 ? r4.z : 0.0};
+        const double A = r4.w;
+        double X[3], U[3];
+        U[0] = P.u[0] + (P.om[1] * r[2] - P.om[2] * r[1]);
+        U[1] = P.u[1] + (P.om[2] * r[0] - P.om[0] * r[2]);
+        U[2] = DIM == 3 ? P.u[2] + (P.om[0] * r[1] - P.om[1] * r[0]) : 0.0;
+        MarkerRec<T> rec;
+        rec.pad = 0;
+        int cb[3][2];
+        T tt[3];
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+            if (d < DIM) {
+                X[d] = P.x[d] + r[d];
+                const double fl = floor(X[d]);
+                rec.b[d] = (int)fl;
+                tt[d] = (T)(X[d] - fl);
+                cb[d][0] = clamp_or_wrap(rec.b[d], nn[d], a.lb.per[d]);
+                cb[d][1] = clamp_or_wrap(rec.b[d] + 1, nn[d], a.lb.per[d]);
+            } else {
+                X[d] = 0; rec.b[d] = 0; tt[d] = 0; cb[d][0] = cb[d][1] = 0;
+            }
+            rec.t[d] = tt[d];
+        }
+        // The interpolation and the exchange are formed in FP64 whatever the
+        // storage: near a steady state T_p - T_l and rho_l U_l - j_l are small
+        // differences of O(1) numbers, and their rounding would act as a
+        // systematic source every step.
+        double rl = 0, jl[3] = {0, 0, 0}, sl = 0;
+#pragma unroll 1
+        for (int c = 0; c < (1 << DIM); ++c) {
+            double W = 1;
+            int ix[3];
+#pragma unroll
+            for (int d = 0; d < 3; ++d) {
+                const int o = (c >> d) & 1;
+                ix[d] = d < DIM ? cb[d][o] : 0;
+                if (d < DIM) W *= o ? tt[d] : 1.0 - tt[d];
+            }
+            using C = typename SF::C;
+            T f[L::Q];
+            C g[L::QG];
+            pull<DIM, SF, T, C>(a.lb, ix[0], ix[1], ix[2], f, g);
+            C drho, j[3], dS;
+            moments<DIM, C>(f, g, drho, j, dS);
+            rl += W * (double)drho;
+#pragma unroll
+            for (int d = 0; d < 3; ++d) jl[d] += W * (double)j[d];
+            sl += W * (double)dS;
+        }
+        const double rho_l = 1.0 + rl;
+        const double dTl = (P.T - a.Tref) - sl;          // T_p - T_l
+        double FA[3];
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+            FA[d] = d < DIM ? 2.0 * (rho_l * U[d] - jl[d]) * A : 0.0;
+            rec.fa[d] = (T)FA[d];
+        }
+        const double QA = 2.0 * a.kappa * dTl * A;
+        rec.qa = (T)QA;
+        a.mk[m0 + m] = rec;
+        s[0] -= FA[0]; s[1] -= FA[1]; s[2] -= FA[2];
+        s[3] -= r[1] * FA[2] - r[2] * FA[1];
+        s[4] -= r[2] * FA[0] - r[0] * FA[2];
+        s[5] -= r[0] * FA[1] - r[1] * FA[0];
+        s[6] += QA;
+        s[7] += dTl * A;
+    }
+    if (!a.react) return;
+#pragma unroll
+    for (int k = 0; k < 8; ++k) red[k][tid] = s[k];
+    __syncthreads();
+    for (int h = 128; h > 0; h >>= 1) {
+        if (tid < h) {
+#pragma unroll
+            for (int k = 0; k < 8; ++k) red[k][tid] += red[k][tid + h];
+        }
+        __syncthreads();
+    }
+    if (tid == 0) {
+        DevReact R;
+        R.F[0] = red[0][0]; R.F[1] = red[1][0]; R.F[2] = DIM == 3 ? red[2][0] : 0.0;
+        R.tq[0] = DIM == 3 ? red[3][0] : 0.0; R.tq[1] = DIM == 3 ? red[4][0] : 0.0; R.tq[2] = red[5][0];
+        R.H = red[6][0]; R.dTA = red[7][0];
+        a.react[p] = R;
+    }
+}
+
+// --------------------------------------------------------------------------
+// K3: bin particles into lattice tiles (integer counting sort).  A particle
+// lands in every tile its markers' spreading footprints can touch: nodes
+// floor(X - rext) - 1 .. floor(X + rext) + 2 per axis.
+// --------------------------------------------------------------------------
+struct BinArgs {
+    int dim, nx, ny, nz, per[3];
+    int TX, TY, TZ, ntx, nty, ntz;
+    int np;
+    const DevParticle *part;
+    const double *tmpl_rext;
+    int *tile_count, *tile_start, *tile_fill, *tile_items;
+    int *err;
+};
+
+constexpr int MAXT_AXIS = 32;
+
+__device__ inline int axis_tiles(double xc, double rext, int n, int per, int T, int *out)
+{
+    const int lo = (int)floor(xc - rext) - 1, hi = (int)floor(xc + rext) + 2;
+    int cnt = 0;
+    for (int c = lo; c <= hi; ++c) {
+        int m = c;
+        if (per) { m %= n; if (m < 0) m += n; }
+        else if (m < 0 || m >= n) continue;
+        const int t = m / T;
+        bool dup = false;
+        for (int k = 0; k < cnt; ++k) dup = dup || out[k] == t;
+        if (!dup && cnt < MAXT_AXIS) out[cnt++] = t;
+    }
+    return cnt;
+}
+
+template <bool FILL>
+__global__ void k_bin(BinArgs a)
+{
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= a.np || halted(a.err)) return;
+    const DevParticle P = a.part[p];
+    const double re = a.tmpl_rext[P.tmpl];
+    // a non-finite or runaway centre would give meaningless loop bounds
+    bool finite = true;
+    for (int d = 0; d < a.dim; ++d) finite = finite && fabs(P.x[d]) < 1.0e8;
+    if (!finite) {
+        if (!FILL) atomicOr(a.err, ERR_DOMAIN);
+        return;
+    }
+    int tx[MAXT_AXIS], ty[MAXT_AXIS], tz[MAXT_AXIS];
+    const int cx = axis_tiles(P.x[0], re, a.nx, a.per[0], a.TX, tx);
+    const int cy = axis_tiles(P.x[1], re, a.ny, a.per[1], a.TY, ty);
+    int cz = 1;
+    tz[0] = 0;
+    if (a.dim == 3) cz = axis_tiles(P.x[2], re, a.nz, a.per[2], a.TZ, tz);
+    for (int k = 0; k < cz; ++k)
+        for (int j = 0; j < cy; ++j)
+            for (int i = 0; i < cx; ++i) {
+                const int t = (tz[k] * a.nty + ty[j]) * a.ntx + tx[i];
+                if (FILL) {
+                    const int pos = atomicAdd(&a.tile_fill[t], 1);
+                    a.tile_items[a.tile_start[t] + pos] = p;
+                } else {
+                    atomicAdd(&a.tile_count[t], 1);
+                }
+            }
+}
+
+__global__ void k_fill_int(int *p, long long n, int v)
+{
+    for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x)
+        p[i] = v;
+}
+
+// Exclusive scan of count[0..n) into start[0..n], one workgroup of 1024.
+// Also clears fill[0..n) for the scatter pass.
+__global__ __launch_bounds__(1024) void k_scan(const int *count, int *start, int *fill, int n)
+{
+    __shared__ int part[1024];
+    const int tid = threadIdx.x;
+    const int chunk = (n + 1023) / 1024;
+    const int b = tid * chunk, e = min(n, b + chunk);
+    int s = 0;
+    for (int i = b; i < e; ++i) s += count[i];
+    part[tid] = s;
+    __syncthreads();
+    for (int off = 1; off < 1024; off <<= 1) {
+        const int v = tid >= off ? part[tid - off] : 0;
+        __syncthreads();
+        part[tid] += v;
+        __syncthreads();
+    }
+    int run = tid == 0 ? 0 : part[tid - 1];
+    for (int i = b; i < e; ++i) {
+        start[i] = run;
+        run += count[i];
+        if (fill) fill[i] = 0;
+    }
+    if (tid == 1023) start[n] = part[1023];
+}
+
+// --------------------------------------------------------------------------
+// K4: DEM cell list and per-particle Verlet list (candidates within
+// R_i + R_j + skin, ascending index for a fixed force-summation order).
+// --------------------------------------------------------------------------
+constexpr int MAXN = 32;           // neighbour candidates per particle
+constexpr int MAXC = 16;           // contact slots per particle (particles + walls)
+
+struct DemArgs {
+    int dim, nx, ny, nz, per[3];
+    int np;
+    int ncx, ncy, ncz;
+    double cwx, cwy, cwz;          // cell widths
+    double skin;
+    const DevParticle *cur;
+    DevParticle *nxt;
+    const DevReact *react;
+    int *cell_count, *cell_start, *cell_fill, *cell_items;
+    int *nbr, *nbr_n;
+    double *xref;                  // 3 per particle: positions at list build
+    const int *hid_in; const double *hxi_in; const int *hn_in;
+    int *hid_out; double *hxi_out; int *hn_out;
+    double E, G, mu, dts;
+    double gravity, beta_p, c_r, Tref;
+    int last;                      // last sub-step: apply the thermosensitive update
+    int *err;
+};
+
+__device__ __forceinline__ int cell_coord(double x, int n, int per, int nc, double cw)
+{
+    double y = x + 0.5;
+    if (per) { y = fmod(y, (double)n); if (y < 0) y += n; }
+    int c = (int)floor(y / cw);
+    return c < 0 ? 0 : (c >= nc ? nc - 1 : c);
+}
+
+template <bool FILL>
+__global__ void k_cells(DemArgs a)
+{
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= a.np || halted(a.err)) return;
+    const DevParticle P = a.cur[p];
+    const int cx = cell_coord(P.x[0], a.nx, a.per[0], a.ncx, a.cwx);
+    const int cy = cell_coord(P.x[1], a.ny, a.per[1], a.ncy, a.cwy);
+    const int cz = a.dim == 3 ? cell_coord(P.x[2], a.nz, a.per[2], a.ncz, a.cwz) : 0;
+    const int c = (cz * a.ncy + cy) * a.ncx + cx;
+    if (FILL) {
+        const int pos = atomicAdd(&a.cell_fill[c], 1);
+        a.cell_items[a.cell_start[c] + pos] = p;
+    } else {
+        atomicAdd(&a.cell_count[c], 1);
+    }
+}
+
+__device__ __forceinline__ void min_image(const DemArgs &a, const double *xi, const double *xj, double *d)
+{
+    const int nn[3] = {a.nx, a.ny, a.nz};
+    for (int c = 0; c < 3; ++c) {
+        d[c] = xj[c] - xi[c];
+        if (c == 2 && a.dim == 2) { d[c] = 0; continue; }
+        if (a.per[c]) {
+            const double L = nn[c];
+            if (d[c] > 0.5 * L) d[c] -= L;
+            else if (d[c] < -0.5 * L) d[c] += L;
+        }
+    }
+}
+
+__device__ inline int axis_cells(int c, int nc, int per, int *out)
+{
+    int cnt = 0;
+    for (int o = -1; o <= 1; ++o) {
+        int m = c + o;
+        if (per) { m %= nc; if (m < 0) m += nc; }
+        else if (m < 0 || m >= nc) continue;
+        bool dup = false;
+        for (int k = 0; k < cnt; ++k) dup = dup || out[k] == m;
+        if (!dup) out[cnt++] = m;
+    }
+    return cnt;
+}
+
+__global__ void k_neighbours(DemArgs a)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= a.np || halted(a.err)) return;
+    const DevParticle P = a.cur[i];
+    const int cx = cell_coord(P.x[0], a.nx, a.per[0], a.ncx, a.cwx);
+    const int cy = cell_coord(P.x[1], a.ny, a.per[1], a.ncy, a.cwy);
+    const int cz = a.dim == 3 ? cell_coord(P.x[2], a.nz, a.per[2], a.ncz, a.cwz) : 0;
+    int lx[3], ly[3], lz[3];
+    const int nx = axis_cells(cx, a.ncx, a.per[0], lx);
+    const int ny = axis_cells(cy, a.ncy, a.per[1], ly);
+    int nz = 1;
+    lz[0] = 0;
+    if (a.dim == 3) nz = axis_cells(cz, a.ncz, a.per[2], lz);
+    int list[MAXN];
+    int n = 0;
+    bool over = false;
+    for (int k = 0; k < nz; ++k)
+        for (int jj = 0; jj < ny; ++jj)
+            for (int ii = 0; ii < nx; ++ii) {
+                const int c = (lz[k] * a.ncy + ly[jj]) * a.ncx + lx[ii];
+                for (int s = a.cell_start[c]; s < a.cell_start[c + 1]; ++s) {
+                    const int j = a.cell_items[s];
+                    if (j == i) continue;
+                    const DevParticle Q = a.cur[j];
+                    double d[3];
+                    min_image(a, P.x, Q.x, d);
+                    const double lim = P.R + Q.R + a.skin;
+                    if (d[0] * d[0] + d[1] * d[1] + d[2] * d[2] < lim * lim) {
+                        if (n < MAXN) {
+                            // insertion keeps ascending order
+                            int pos = n++;
+                            while (pos > 0 && list[pos - 1] > j) { list[pos] = list[pos - 1]; --pos; }
+                            list[pos] = j;
+                        } else over = true;
+                    }
+                }
+            }
+    for (int k = 0; k < n; ++k) a.nbr[(size_t)i * MAXN + k] = list[k];
+    a.nbr_n[i] = n;
+    a.xref[3 * i] = P.x[0]; a.xref[3 * i + 1] = P.x[1]; a.xref[3 * i + 2] = P.x[2];
+    if (over) atomicOr(a.err, ERR_NEIGHBOURS);
+}
+
+// --------------------------------------------------------------------------
+// K5: one DEM sub-step per launch, state double-buffered (cur -> nxt).
+// Hertz normal force F_n = 4/3 E* sqrt(R*) delta^(3/2) (Sec. 2.3);
+// tangential spring with stiffness 8 G* sqrt(R* delta) (the
+// Mindlin-Deresiewicz increment in its no-slip limit) capped by mu F_n, with
+// G* = (1 - nu) E* / (2 (2 - nu)) for equal materials; semi-implicit Euler
+// of Eq. (demgov) with the particle mass on the gravity term.
+// --------------------------------------------------------------------------
+__device__ inline void contact(const DemArgs &a, double Ri, const double *n, double delta, double Rstar,
+                               const double *vrel, const double *xi_old, double *F, double *Tq, double *xi)
+{
+    const double Fn = 4.0 / 3.0 * a.E * sqrt(Rstar) * delta * sqrt(delta);
+    const double vn = vrel[0] * n[0] + vrel[1] * n[1] + vrel[2] * n[2];
+    const double vt[3] = {vrel[0] - vn * n[0], vrel[1] - vn * n[1], vrel[2] - vn * n[2]};
+    double x[3] = {xi_old[0], xi_old[1], xi_old[2]};
+    const double xn = x[0] * n[0] + x[1] * n[1] + x[2] * n[2];
+    for (int c = 0; c < 3; ++c) x[c] = x[c] - xn * n[c] + vt[c] * a.dts;
+    const double kt = 8.0 * a.G * sqrt(Rstar * delta);
+    double Ft[3] = {-kt * x[0], -kt * x[1], -kt * x[2]};
+    const double ft = sqrt(Ft[0] * Ft[0] + Ft[1] * Ft[1] + Ft[2] * Ft[2]);
+    const double cap = a.mu * Fn;
+    if (ft > cap) {
+        const double sc = cap / ft;
+        for (int c = 0; c < 3; ++c) { Ft[c] *= sc; x[c] = -Ft[c] / kt; }
+    }
+    for (int c = 0; c < 3; ++c) { F[c] = -Fn * n[c] + Ft[c]; xi[c] = x[c]; }
+    const double rn[3] = {Ri * n[0], Ri * n[1], Ri * n[2]};
+    Tq[0] = rn[1] * Ft[2] - rn[2] * Ft[1];
+    Tq[1] = rn[2] * Ft[0] - rn[0] * Ft[2];
+    Tq[2] = rn[0] * Ft[1] - rn[1] * Ft[0];
+}
+
+__global__ void k_dem(DemArgs a)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= a.np) return;
+    const DevParticle P = a.cur[i];
+    if (halted(a.err)) {
+        a.nxt[i] = P;                  // keep both particle copies identical
+        a.hn_out[i] = a.hn_in[i];
+        for (int s = 0; s < a.hn_in[i] && s < MAXC; ++s) {
+            const size_t k = (size_t)i * MAXC + s;
+            a.hid_out[k] = a.hid_in[k];
+            a.hxi_out[3 * k] = a.hxi_in[3 * k]; a.hxi_out[3 * k + 1] = a.hxi_in[3 * k + 1]; a.hxi_out[3 * k + 2] = a.hxi_in[3 * k + 2];
+        }
+        return;
+    }
+    const int dim = a.dim;
+    const int nold = a.hn_in[i];
+    double Fc[3] = {0, 0, 0}, Tc[3] = {0, 0, 0};
+    int nnew = 0;
+    bool over = false;
+    const size_t hb = (size_t)i * MAXC;
+    auto find_old = [&](int partner, double *xo) {
+        xo[0] = xo[1] = xo[2] = 0.0;
+        for (int s = 0; s < nold; ++s)
+            if (a.hid_in[hb + s] == partner) {
+                xo[0] = a.hxi_in[3 * (hb + s)]; xo[1] = a.hxi_in[3 * (hb + s) + 1]; xo[2] = a.hxi_in[3 * (hb + s) + 2];
+                return;
+            }
+    };
+    auto record = [&](int partner, const double *xi) {
+        if (nnew < MAXC) {
+            a.hid_out[hb + nnew] = partner;
+            a.hxi_out[3 * (hb + nnew)] = xi[0]; a.hxi_out[3 * (hb + nnew) + 1] = xi[1]; a.hxi_out[3 * (hb + nnew) + 2] = xi[2];
+            ++nnew;
+        } else over = true;
+    };
+    const double wiP[3] = {P.om[0], P.om[1], P.om[2]};
+    const int nn = a.nbr_n[i];
+    for (int k = 0; k < nn; ++k) {
+        const int j = a.nbr[(size_t)i * MAXN + k];
+        const DevParticle Q = a.cur[j];
+        double d[3];
+        min_image(a, P.x, Q.x, d);
+        const double dist = sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
+        if (!(dist < P.R + Q.R)) continue;
+        const double n[3] = {d[0] / dist, d[1] / dist, d[2] / dist};
+        const double delta = P.R + Q.R - dist;
+        const double Rstar = P.R * Q.R / (P.R + Q.R);
+        const double ri[3] = {P.R * n[0], P.R * n[1], P.R * n[2]};
+        const double rj[3] = {Q.R * n[0], Q.R * n[1], Q.R * n[2]};
+        const double wi[3] = {wiP[1] * ri[2] - wiP[2] * ri[1], wiP[2] * ri[0] - wiP[0] * ri[2], wiP[0] * ri[1] - wiP[1] * ri[0]};
+        const double wj[3] = {Q.om[1] * rj[2] - Q.om[2] * rj[1], Q.om[2] * rj[0] - Q.om[0] * rj[2], Q.om[0] * rj[1] - Q.om[1] * rj[0]};
+        double vrel[3];
+        for (int c = 0; c < 3; ++c) vrel[c] = (P.u[c] - Q.u[c]) + (wi[c] + wj[c]);
+        double xo[3], F[3], T[3], xn[3];
+        find_old(j, xo);
+        contact(a, P.R, n, delta, Rstar, vrel, xo, F, T, xn);
+        for (int c = 0; c < 3; ++c) { Fc[c] += F[c]; Tc[c] += T[c]; }
+        record(j, xn);
+    }
+    const int nn3[3] = {a.nx, a.ny, a.nz};
+    for (int ax = 0; ax < dim; ++ax) {
+        if (a.per[ax]) continue;
+        for (int side = 0; side < 2; ++side) {
+            const double gap = side == 0 ? P.x[ax] + 0.5 : (nn3[ax] - 0.5) - P.x[ax];
+            const double delta = P.R - gap;
+            if (!(delta > 0)) continue;
+            double n[3] = {0, 0, 0};
+            n[ax] = side == 0 ? -1.0 : 1.0;
+            const double ri[3] = {P.R * n[0], P.R * n[1], P.R * n[2]};
+            const double wi[3] = {wiP[1] * ri[2] - wiP[2] * ri[1], wiP[2] * ri[0] - wiP[0] * ri[2], wiP[0] * ri[1] - wiP[1] * ri[0]};
+            double vrel[3];
+            for (int c = 0; c < 3; ++c) vrel[c] = P.u[c] + wi[c];
+            const int partner = -1 - (2 * ax + side);
+            double xo[3], F[3], T[3], xn[3];
+            find_old(partner, xo);
+            contact(a, P.R, n, delta, P.R, vrel, xo, F, T, xn);
+            for (int c = 0; c < 3; ++c) { Fc[c] += F[c]; Tc[c] += T[c]; }
+            record(partner, xn);
+        }
+    }
+    a.hn_out[i] = nnew;
+    DevParticle O = P;
+    const DevReact Rh = a.react[i];
+    if (!(P.flags & 1)) {
+        const double pi = 3.14159265358979323846;
+        const double V = dim == 2 ? pi * P.R * P.R : 4.0 / 3.0 * pi * P.R * P.R * P.R;
+        const double m = P.rho_r * V;
+        const double I = dim == 2 ? 0.5 * m * P.R * P.R : 0.4 * m * P.R * P.R;
+        double rho_p = P.rho_r;
+        if (P.flags & 2) rho_p = P.rho_r * (1.0 - a.beta_p * (P.T - a.Tref));
+        double gv[3] = {0, 0, 0};
+        gv[dim - 1] = -a.gravity * (1.0 - 1.0 / rho_p);
+        for (int c = 0; c < dim; ++c) {
+            O.u[c] = P.u[c] + a.dts * ((Rh.F[c] + Fc[c]) / m + gv[c]);
+            O.x[c] = P.x[c] + a.dts * O.u[c];
+        }
+        if (dim == 2) {
+            O.om[2] = P.om[2] + a.dts * (Rh.tq[2] + Tc[2]) / I;
+            O.th[2] = P.th[2] + a.dts * O.om[2];
+        } else {
+            for (int c = 0; c < 3; ++c) {
+                O.om[c] = P.om[c] + a.dts * (Rh.tq[c] + Tc[c]) / I;
+                O.th[c] = P.th[c] + a.dts * O.om[c];
+            }
+        }
+    }
+    if (a.last && (P.flags & 2)) {
+        const double pi = 3.14159265358979323846;
+        const double V = dim == 2 ? pi * P.R * P.R : 4.0 / 3.0 * pi * P.R * P.R * P.R;
+        O.T = P.T - Rh.H / (P.rho_r * a.c_r * V);
+    }
+    a.nxt[i] = O;
+    // watchdog: stale neighbour list, NaN, centre beyond a wall
+    double dd[3];
+    const double xr[3] = {a.xref[3 * i], a.xref[3 * i + 1], a.xref[3 * i + 2]};
+    min_image(a, xr, O.x, dd);
+    int e = 0;
+    if (!(dd[0] * dd[0] + dd[1] * dd[1] + dd[2] * dd[2] <= 0.25 * a.skin * a.skin)) e |= ERR_STALE;
+    for (int c = 0; c < dim; ++c) {
+        if (!a.per[c] && !(O.x[c] > -0.5 && O.x[c] < nn3[c] - 0.5)) e |= ERR_DOMAIN;
+        if (!(fabs(O.x[c]) < 1.0e8) || !(fabs(O.u[c]) < 1.0e8)) e |= ERR_DOMAIN;
+    }
+    if (over) e |= ERR_CONTACTS;
+    if (e) atomicOr(a.err, e);
+}
+
+// Initial state: f = w rho0 and g = w T_init, i.e. deviations 0 and
+// w (T_init - T_ref).
+template <class SF, int QG>
+__global__ void k_init(void *f, void *g, int Q, long long N, long long Ns, typename SF::T dTinit, double wg0, double wg1)
+{
+    using S = typename SF::S;
+    for (long long n = blockIdx.x * (long long)blockDim.x + threadIdx.x; n < N; n += (long long)gridDim.x * blockDim.x) {
+        for (int q = 0; q < Q; ++q) SF::st((S *)f + (size_t)q * Ns, n, (typename SF::T)0, 1.0);
+        for (int q = 0; q < QG; ++q) {
+            const double w = q == 0 ? wg0 : wg1;
+            SF::st((S *)g + (size_t)q * Ns, n, (typename SF::T)(w * (double)dTinit), w);
+        }
+    }
+}
+
+}  // namespace pibm

@@ -206,7 +206,7 @@ def workload(name: str):
     if name == "c4":
         return thermo_3d()
     if name == "c4_small":
-        return thermo_3d(n=40, n_spheres=10, D=8.0, seed=14)
+        return thermo_3d(n=48, n_spheres=9, D=10.0, seed=14)
     raise KeyError(name)
 
 
