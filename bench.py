@@ -117,6 +117,7 @@ def main() -> int:
     ap.add_argument("--variants", default="f16,bf16", help="extra storage formats timed beside the main one")
     ap.add_argument("--cpu-steps", type=int, default=2)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--empty", action="store_true", help="analysis: the same lattice without particles")
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
@@ -127,6 +128,8 @@ def main() -> int:
     from paper_1502_01159_amd import workloads as W
 
     cfg, P = W.workload(args.workload)
+    if args.empty:
+        P = P[:0]
     main_run = time_gpu(cfg, P, args.storage, args.steps, args.warmup, profile=True)
     N, Q, Qg = main_run["N"], main_run["Q"], main_run["Qg"]
     ms_step = main_run["ms"] / args.steps

@@ -90,6 +90,7 @@ __device__ __forceinline__ float unit_hash(uint32_t n, uint32_t q, uint32_t step
 // --------------------------------------------------------------------------
 struct StF32 {
     using S = float; using T = float; using C = double;
+    static __device__ __forceinline__ T cvt(S v, double) { return v; }
     static __device__ __forceinline__ T ld(const S *p, size_t i, double) { return p[i]; }
     static __device__ __forceinline__ void st(S *p, size_t i, T v, double) { p[i] = v; }
     template <class A, class I>
@@ -107,6 +108,7 @@ struct StF32 {
 };
 struct StF64 {
     using S = double; using T = double; using C = double;
+    static __device__ __forceinline__ T cvt(S v, double) { return v; }
     static __device__ __forceinline__ T ld(const S *p, size_t i, double) { return p[i]; }
     static __device__ __forceinline__ void st(S *p, size_t i, T v, double) { p[i] = v; }
     template <class A, class I>
@@ -135,6 +137,7 @@ struct StF16 {
     using S = __half; using T = float; using C = float;
     static __device__ __forceinline__ float dec(uint16_t b) { __half h; __builtin_memcpy(&h, &b, 2); return __half2float(h); }
     static __device__ __forceinline__ uint16_t enc(float v) { __half h = __float2half_rn(v); uint16_t b; __builtin_memcpy(&b, &h, 2); return b; }
+    static __device__ __forceinline__ T cvt(S v, double w) { return __half2float(v) * (float)w; }
     static __device__ __forceinline__ T ld(const S *p, size_t i, double w) { return __half2float(p[i]) * (float)w; }
     static __device__ __forceinline__ void st(S *p, size_t i, T v, double w) { p[i] = __float2half_rn(v * (float)(1.0 / w)); }
     template <class A, class I>
@@ -149,6 +152,7 @@ struct StF16 {
 };
 struct StBF16 {
     using S = uint16_t; using T = float; using C = float;
+    static __device__ __forceinline__ T cvt(S v, double w) { return __uint_as_float(((uint32_t)v) << 16) * (float)w; }
     static __device__ __forceinline__ T ld(const S *p, size_t i, double w) {
         return __uint_as_float(((uint32_t)p[i]) << 16) * (float)w;
     }
@@ -257,7 +261,10 @@ __device__ __forceinline__ void nbr_axis(int c, int n, int per, int &m, int &p, 
 
 // Pull streaming (Eqs. lbm2, lbm2.5 read at the arrival node): deviation
 // populations of node (x, y, z) after streaming, with halfway bounce-back for
-// f and anti-bounce-back (Dirichlet wall temperature) for g.
+// f and anti-bounce-back (Dirichlet wall temperature) for g.  Branch-free:
+// every direction loads from one selected address (the upstream node in its
+// own array, or this node in the opposite direction's array at a wall), so
+// all loads of a node are in flight together.
 template <int DIM, class SF, class T, class TG>
 __device__ __forceinline__ void pull(const LbmArgs<T> &a, int x, int y, int z, T *f, TG *g)
 {
@@ -270,37 +277,44 @@ __device__ __forceinline__ void pull(const LbmArgs<T> &a, int x, int y, int z, T
     nbr_axis(y, a.ny, a.per[1], nb.m[1], nb.p[1], nb.vm[1], nb.vp[1]);
     if (DIM == 3) nbr_axis(z, a.nz, a.per[2], nb.m[2], nb.p[2], nb.vm[2], nb.vp[2]);
     else { nb.m[2] = nb.p[2] = 0; nb.vm[2] = nb.vp[2] = true; }
-    const int c[3] = {x, y, z};
-    const size_t sxy = (size_t)a.nx * a.ny;
-    const size_t self = (size_t)z * sxy + (size_t)y * a.nx + x;
+    const long long nx = a.nx, sxy = (long long)a.nx * a.ny;
+    // linear offsets of the upstream coordinate per axis: index by e + 1
+    const long long ox[3] = {(long long)nb.p[0], (long long)x, (long long)nb.m[0]};
+    const long long oy[3] = {nb.p[1] * nx, y * nx, nb.m[1] * nx};
+    const long long oz[3] = {nb.p[2] * sxy, z * sxy, nb.m[2] * sxy};
+    const bool vx[3] = {nb.vp[0], true, nb.vm[0]};
+    const bool vy[3] = {nb.vp[1], true, nb.vm[1]};
+    const bool vz[3] = {nb.vp[2], true, nb.vm[2]};
+    const long long self = oz[1] + oy[1] + ox[1];
+    S fr[L::Q], gr[L::QG];
+    bool gv[L::QG];
 #pragma unroll
     for (int q = 0; q < L::Q; ++q) {
-        int s[3];
-        bool v = true;
-#pragma unroll
-        for (int d = 0; d < 3; ++d) {
-            const int e = L::e(q, d);
-            s[d] = e > 0 ? nb.m[d] : (e < 0 ? nb.p[d] : c[d]);
-            v = v && (e > 0 ? nb.vm[d] : (e < 0 ? nb.vp[d] : true));
-        }
-        if (v) f[q] = SF::ld(fa + (size_t)q * a.Ns, (size_t)s[2] * sxy + (size_t)s[1] * a.nx + s[0], L::w(q));
-        else f[q] = SF::ld(fa + (size_t)L::opp(q) * a.Ns, self, L::w(q));
+        const int ex = L::e(q, 0) + 1, ey = L::e(q, 1) + 1, ez = L::e(q, 2) + 1;
+        const bool v = vx[ex] && vy[ey] && vz[ez];
+        const S *src = v ? fa + (long long)q * a.Ns + (oz[ez] + oy[ey] + ox[ex])
+                         : fa + (long long)L::opp(q) * a.Ns + self;
+        fr[q] = *src;
     }
 #pragma unroll
     for (int q = 0; q < L::QG; ++q) {
-        int s[3];
-        bool v = true;
-        int face = 0;
+        const int ex = L::e(q, 0) + 1, ey = L::e(q, 1) + 1, ez = L::e(q, 2) + 1;
+        gv[q] = vx[ex] && vy[ey] && vz[ez];
+        const S *src = gv[q] ? ga + (long long)q * a.Ns + (oz[ez] + oy[ey] + ox[ex])
+                             : ga + (long long)L::opp(q) * a.Ns + self;
+        gr[q] = *src;
+    }
+    // every load of the node is issued before any value is used
+    __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
-        for (int d = 0; d < 3; ++d) {
-            const int e = L::e(q, d);
-            s[d] = e > 0 ? nb.m[d] : (e < 0 ? nb.p[d] : c[d]);
-            const bool ok = e > 0 ? nb.vm[d] : (e < 0 ? nb.vp[d] : true);
-            if (e != 0) face = 2 * d + (e > 0 ? 0 : 1);
-            v = v && ok;
-        }
-        if (v) g[q] = (TG)SF::ld(ga + (size_t)q * a.Ns, (size_t)s[2] * sxy + (size_t)s[1] * a.nx + s[0], L::wg(q));
-        else g[q] = -(TG)SF::ld(ga + (size_t)L::opp(q) * a.Ns, self, L::wg(q)) + (TG)(2.0 * L::wg(q) * a.tw[face]);
+    for (int q = 0; q < L::Q; ++q) f[q] = SF::cvt(fr[q], L::w(q));
+#pragma unroll
+    for (int q = 0; q < L::QG; ++q) {
+        // the one axis of a D2Q5 / D3Q7 direction decides the wall face
+        const int d = L::e(q, 0) != 0 ? 0 : (L::e(q, 1) != 0 ? 1 : 2);
+        const int face = 2 * d + (L::e(q, d) > 0 ? 0 : 1);
+        const TG val = (TG)SF::cvt(gr[q], L::wg(q));
+        g[q] = gv[q] ? val : -val + (TG)(2.0 * L::wg(q) * a.tw[q == 0 ? 0 : face]);
     }
 }
 

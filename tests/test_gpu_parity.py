@@ -231,15 +231,16 @@ def test_rest_state_exact_in_f32(gpu):
 # --------------------------------------------------------------------------- #
 
 def _crop(cfg, P, centre, half):
-    """Periodic crop of side 2*half around `centre` holding every particle whose
-    spreading footprint reaches into it."""
+    """Periodic crop of side 2*half around `centre` holding the particles that
+    lie entirely inside it (so that none meets a periodic image of another:
+    such spurious contacts would travel inward through the DEM sub-steps)."""
     lo = np.floor(np.array(centre) - half).astype(int)
     n = 2 * half
     c2 = dict(cfg, nx=n, ny=n, nz=n, periodic=[1, 1, 1])
     keep = []
     for r in P:
         x = r[:3] - lo
-        if np.all(x > -r[9] - 3) and np.all(x < n + r[9] + 3):
+        if np.all(x >= r[9] + 1) and np.all(x <= n - r[9] - 1):
             rr = r.copy()
             rr[:3] = x
             keep.append(rr)
