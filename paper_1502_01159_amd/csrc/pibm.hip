@@ -366,6 +366,7 @@ int launch_markers(pibm_ctx *c, bool reactions)
     m.part = (const DevParticle *)c->r(c->pcur ? R_PART1 : R_PART0);
     m.tmpl = (const double4 *)c->r(R_TMPL);
     m.tmpl_start = (const int *)c->r(R_TMPL_START);
+    m.tmpl_rext = (const double *)c->r(R_TMPL_REXT);
     m.mk_start = (const int *)c->r(R_MK_START);
     m.mk = (MarkerRec<T> *)c->r(R_MK);
     m.react = reactions ? (DevReact *)c->r(R_REACT) : nullptr;
@@ -403,6 +404,8 @@ int launch_bin(pibm_ctx *c)
     hipLaunchKernelGGL((k_bin<false>), dim3(gb), dim3(128), 0, c->stream, b);
     hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, c->stream, (const int *)b.tile_count, b.tile_start, b.tile_fill, nt);
     hipLaunchKernelGGL((k_bin<true>), dim3(gb), dim3(128), 0, c->stream, b);
+    hipLaunchKernelGGL(k_sort_lists, dim3((nt + 255) / 256), dim3(256), 0, c->stream, (const int *)b.tile_start,
+                       b.tile_items, nt);
     return hip_ok(c, hipGetLastError());
 }
 

@@ -188,7 +188,7 @@ struct DevReact {                  // per-particle reactions of the last step
 template <typename T> struct alignas(16) MarkerRec {
     int b[3];                      // floor(X_l) per axis (unwrapped)
     int pad;
-    T t[3];                        // X_l - floor(X_l)
+    T w[3][4];                     // cosine-kernel weights of nodes b-1 .. b+2 per axis
     T fa[3];                       // F_l A_l (force density times weight)
     T qa;                          // Q_l A_l
 };
@@ -219,10 +219,14 @@ constexpr int TILE_X = 64;
 template <int DIM> struct Tile {
     static constexpr int X = TILE_X, Y = DIM == 3 ? 4 : 16, Z = DIM == 3 ? 4 : 1;
     static constexpr int N = X * Y * Z;           // 1024 nodes, 4 per thread
+    // LDS layout of the tile's spread force: rows padded to 68 words so that
+    // a marker footprint (4 x 4 x 4 nodes, one per lane) lands on 64
+    // distinct banks: offset = x + 68 y + 272 z = x + 4 y + 16 z (mod 64).
+    static constexpr int PY = X + 4, PZ = PY * Y;
+    static constexpr int NPAD = PZ * Z;
+    static __host__ __device__ constexpr int lds(int x, int y, int z) { return x + PY * y + PZ * z; }
 };
 constexpr int LBM_THREADS = 256;
-constexpr double FIX_SCALE = 281474976710656.0;       // 2^48
-constexpr double FIX_INV = 1.0 / 281474976710656.0;
 
 template <typename T> struct LbmArgs {
     int nx, ny, nz;
@@ -362,19 +366,50 @@ __device__ __forceinline__ int wrap_or_out(int c, int n, int per)
     return (c < 0 || c >= n) ? -1 : c;
 }
 
-__device__ __forceinline__ unsigned long long to_fix(double v)
-{
-    return (unsigned long long)__double2ll_rn(v * FIX_SCALE);
-}
 
 // --------------------------------------------------------------------------
 // K1: fused pull-stream + moments + PIBM spreading (Eqs. lbm10-lbm12,
 // lbm12.6) + buoyancy + Guo-forced BGK for f (lbm2, lbm3, lbm9) and
 // source-forced BGK for g (lbm2.5, lbm12.5).  One workgroup per 1024-node
-// tile; the tile's spread force and heat are accumulated in LDS as 2^-48
-// fixed point (order-independent, hence bitwise reproducible) and never
-// written to HBM.
+// tile.  Spreading: each wave tests 64 markers at a time against the tile
+// and, for every hit, lays the marker's 4^d footprint across its lanes (one
+// node per lane) and adds into its own LDS copy of the tile's force and heat
+// (plain read-add-write: no two lanes share a node, and one wave's LDS
+// operations complete in order); the copies are summed in a fixed order, so
+// with the tile lists sorted the result is reproducible bit for bit.  Nothing
+// of it is written to HBM.
 // --------------------------------------------------------------------------
+// Value of `v` in lane `k` (wave-uniform k), through the scalar unit.
+__device__ __forceinline__ float lane_bcast(float v, int k)
+{
+    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), k));
+}
+__device__ __forceinline__ double lane_bcast(double v, int k)
+{
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffffll), k);
+    const int hi = __builtin_amdgcn_readlane((int)(b >> 32), k);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
+constexpr int XCD_CHUNK = 8;
+__device__ __forceinline__ int xcd_tile(int b, int G)
+{
+    const int span = 8 * XCD_CHUNK;
+    const int main = G - G % span;
+    if (b >= main) return b;
+    const int xcd = b & 7, slot = b >> 3;
+    return (slot / XCD_CHUNK) * span + xcd * XCD_CHUNK + slot % XCD_CHUNK;
+}
+
+template <int DIM, class SF> struct SpreadLds {
+    using T = typename SF::T;
+    static constexpr int NC = DIM + 1;
+    // one copy per wave for 4-byte accumulators; one shared copy (LDS atomics,
+    // summation order not fixed) for the FP64 parity path
+    static constexpr int NCOPY = sizeof(T) == 4 ? LBM_THREADS / 64 : 1;
+};
+
 template <int DIM, class SF, bool MACRO>
 __global__ __launch_bounds__(LBM_THREADS) void k_lbm(LbmArgs<typename SF::T> a)
 {
@@ -382,13 +417,14 @@ __global__ __launch_bounds__(LBM_THREADS) void k_lbm(LbmArgs<typename SF::T> a)
     using L = Lat<DIM>;
     using TL = Tile<DIM>;
     constexpr int NC = DIM + 1;
-    __shared__ unsigned long long acc[NC * TL::N];
+    constexpr int NCOPY = SpreadLds<DIM, SF>::NCOPY;
+    __shared__ T acc[NCOPY][NC][TL::NPAD];
 
-    // XCD-aware order: consecutive workgroups go to different XCDs; give each
-    // XCD a contiguous run of tiles so that neighbours share an L2.
-    const int G = gridDim.x, b = blockIdx.x;
-    const int q8 = G >> 3, r8 = G & 7, xcd = b & 7, slot = b >> 3;
-    const int t = xcd * q8 + (xcd < r8 ? xcd : r8) + slot;
+    // XCD-aware order: consecutive workgroups go to different XCDs (round
+    // robin over 8); give each XCD runs of XCD_CHUNK consecutive tiles so that
+    // x-neighbours share an L2, while the runs interleave over the domain so
+    // that regions dense in particles are spread over all XCDs.
+    const int t = xcd_tile(blockIdx.x, gridDim.x);
     const int tx = t % a.ntx, rem = t / a.ntx, ty = rem % a.nty, tz = rem / a.nty;
     const int x0 = tx * TL::X, y0 = ty * TL::Y, z0 = tz * TL::Z;
     const int tid = threadIdx.x;
@@ -397,53 +433,70 @@ __global__ __launch_bounds__(LBM_THREADS) void k_lbm(LbmArgs<typename SF::T> a)
     const int ps = a.tile_start[t], pe = a.tile_start[t + 1];
     const bool has = pe > ps;
     if (has) {
-        for (int i = tid; i < NC * TL::N; i += LBM_THREADS) acc[i] = 0ull;
+        for (int i = tid; i < NCOPY * NC * TL::NPAD; i += LBM_THREADS) (&acc[0][0][0])[i] = (T)0;
         __syncthreads();
+        const int lane = tid & 63, wv = tid >> 6;
+        const int cp = NCOPY == 1 ? 0 : wv;
         const int org[3] = {x0, y0, z0};
         const int ext[3] = {TL::X, TL::Y, TL::Z};
         const int nn[3] = {a.nx, a.ny, a.nz};
+        // this lane's offset inside a marker footprint
+        const int kxyz[3] = {lane & 3, (lane >> 2) & 3, DIM == 3 ? (lane >> 4) : 0};
+        const bool lane_on = DIM == 3 || lane < 16;
         for (int e = ps; e < pe; ++e) {
             const int p = a.tile_items[e];
-            const int m1 = a.mk_start[p + 1];
-            for (int m = a.mk_start[p] + tid; m < m1; m += LBM_THREADS) {
-                const MarkerRec<T> r = a.mk[m];
-                int loc[3][4];
-                double wt[3][4];
-                bool any = true;
+            const int m0 = a.mk_start[p], m1 = a.mk_start[p + 1];
+            for (int base = m0 + wv * 64; base < m1; base += LBM_THREADS) {
+                const int m = base + lane;
+                bool hit = m < m1;
+                MarkerRec<T> rec;
+                if (hit) {
+                    rec = a.mk[m];
 #pragma unroll
-                for (int d = 0; d < 3; ++d) {
-                    if (d >= DIM) {
-                        loc[d][0] = 0; loc[d][1] = loc[d][2] = loc[d][3] = -1;
-                        wt[d][0] = 1; wt[d][1] = wt[d][2] = wt[d][3] = 0;
-                        continue;
-                    }
-                    bool hit = false;
+                    for (int d = 0; d < DIM; ++d) {
+                        bool any = false;
 #pragma unroll
-                    for (int k = 0; k < 4; ++k) {
-                        const int gc = wrap_or_out(r.b[d] - 1 + k, nn[d], a.per[d]);
-                        const int l = gc - org[d];
-                        loc[d][k] = (gc >= 0 && l >= 0 && l < ext[d]) ? l : -1;
-                        hit = hit || loc[d][k] >= 0;
+                        for (int k = 0; k < 4; ++k) {
+                            const int l = wrap_or_out(rec.b[d] - 1 + k, nn[d], a.per[d]) - org[d];
+                            any = any || (l >= 0 && l < ext[d]);
+                        }
+                        hit = hit && any;
                     }
-                    any = any && hit;
                 }
-                if (!any) continue;
+                unsigned long long mask = __ballot(hit);
+                while (mask) {
+                    // the hit lane's record, broadcast to the whole wave
+                    const int k = __ffsll((unsigned long long)mask) - 1;
+                    mask &= mask - 1;
+                    int loc = 0;
+                    bool in = lane_on;
+                    T W = (T)1;
 #pragma unroll
-                for (int d = 0; d < DIM; ++d) cos_weights((double)r.t[d], wt[d]);
+                    for (int d = 0; d < DIM; ++d) {
+                        const int bd = __builtin_amdgcn_readlane(rec.b[d], k);
+                        const int l = wrap_or_out(bd - 1 + kxyz[d], nn[d], a.per[d]) - org[d];
+                        in = in && l >= 0 && l < ext[d];
+                        loc += (d == 0 ? l : (d == 1 ? TL::PY * l : TL::PZ * l));
+                        const T w0 = lane_bcast(rec.w[d][0], k), w1 = lane_bcast(rec.w[d][1], k);
+                        const T w2 = lane_bcast(rec.w[d][2], k), w3 = lane_bcast(rec.w[d][3], k);
+                        const int kk = kxyz[d];
+                        W *= kk == 0 ? w0 : (kk == 1 ? w1 : (kk == 2 ? w2 : w3));
+                    }
+                    T fa[DIM], qa;
 #pragma unroll
-                for (int kz = 0; kz < (DIM == 3 ? 4 : 1); ++kz) {
-                    if (loc[2][kz] < 0) continue;
+                    for (int c = 0; c < DIM; ++c) fa[c] = lane_bcast(rec.fa[c], k);
+                    qa = lane_bcast(rec.qa, k);
+                    if (in) {
+                        if (NCOPY > 1) {
+                            // private copy of this wave, distinct node per lane:
+                            // a plain read-add-write (LDS atomics run lane by lane)
 #pragma unroll
-                    for (int ky = 0; ky < 4; ++ky) {
-                        if (loc[1][ky] < 0) continue;
+                            for (int c = 0; c < DIM; ++c) acc[cp][c][loc] += fa[c] * W;
+                            acc[cp][DIM][loc] += qa * W;
+                        } else {
 #pragma unroll
-                        for (int kx = 0; kx < 4; ++kx) {
-                            if (loc[0][kx] < 0) continue;
-                            const int idx = loc[0][kx] + TL::X * (loc[1][ky] + TL::Y * loc[2][kz]);
-                            const double W = wt[0][kx] * wt[1][ky] * wt[2][kz];
-#pragma unroll
-                            for (int c = 0; c < DIM; ++c) atomicAdd(&acc[c * TL::N + idx], to_fix((double)r.fa[c] * W));
-                            atomicAdd(&acc[DIM * TL::N + idx], to_fix((double)r.qa * W));
+                            for (int c = 0; c < DIM; ++c) atomicAdd(&acc[cp][c][loc], fa[c] * W);
+                            atomicAdd(&acc[cp][DIM][loc], qa * W);
                         }
                     }
                 }
@@ -468,9 +521,15 @@ __global__ __launch_bounds__(LBM_THREADS) void k_lbm(LbmArgs<typename SF::T> a)
         C FB[3] = {0, 0, 0};
         C QB = 0;
         if (has) {
+            const int li = TL::lds(lx, ly, lz);
 #pragma unroll
-            for (int c = 0; c < DIM; ++c) FB[c] = (C)((double)(long long)acc[c * TL::N + ln] * FIX_INV);
-            QB = (C)((double)(long long)acc[DIM * TL::N + ln] * FIX_INV);
+            for (int c = 0; c < NC; ++c) {
+                T v = acc[0][c][li];
+#pragma unroll
+                for (int w = 1; w < NCOPY; ++w) v += acc[w][c][li];   // fixed order
+                if (c < DIM) FB[c] = (C)v;
+                else QB = (C)v;
+            }
         }
         T f[L::Q];
         C g[L::QG];
@@ -552,6 +611,7 @@ template <typename T> struct MkArgs {
     const DevParticle *part;
     const double4 *tmpl;           // r_l (x, y, z) and A_l
     const int *tmpl_start;
+    const double *tmpl_rext;       // largest |r_l| component per template
     const int *mk_start;
     MarkerRec<T> *mk;
     DevReact *react;               // NULL in the macro pass
@@ -564,45 +624,145 @@ __device__ __forceinline__ int clamp_or_wrap(int c, int n, int per)
     return c < 0 ? 0 : (c >= n ? n - 1 : c);
 }
 
+// Lagrangian-point set-up shared by both gathering modes: position, rigid
+// velocity U_l = U_p + Omega x r_l, stencil base and fractions, and the
+// cosine-kernel weights stored for K1.
+template <int DIM, class T>
+__device__ __forceinline__ void marker_setup(const DevParticle &P, const double4 &r4, double *r, double *U,
+                                             MarkerRec<T> &rec, double *tt)
+{
+    r[0] = r4.x; r[1] = r4.y; r[2] = DIM == 3 ? r4.z : 0.0;
+    U[0] = P.u[0] + (P.om[1] * r[2] - P.om[2] * r[1]);
+    U[1] = P.u[1] + (P.om[2] * r[0] - P.om[0] * r[2]);
+    U[2] = DIM == 3 ? P.u[2] + (P.om[0] * r[1] - P.om[1] * r[0]) : 0.0;
+    rec.pad = 0;
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+        if (d < DIM) {
+            const double X = P.x[d] + r[d];
+            const double fl = floor(X);
+            rec.b[d] = (int)fl;
+            tt[d] = X - fl;
+            double wk[4];
+            cos_weights(tt[d], wk);
+#pragma unroll
+            for (int k = 0; k < 4; ++k) rec.w[d][k] = (T)wk[k];
+        } else {
+            rec.b[d] = 0; tt[d] = 0;
+            rec.w[d][0] = (T)1; rec.w[d][1] = rec.w[d][2] = rec.w[d][3] = (T)0;
+        }
+    }
+}
+
+constexpr int K2_MAXBOX = 16384;    // cells of a particle's stencil box (bitmap)
+constexpr int K2_MAXSHELL = 2048;   // distinct stencil nodes kept in LDS
+
 template <int DIM, class SF>
 __global__ __launch_bounds__(256) void k_markers(MkArgs<typename SF::T> a)
 {
     using T = typename SF::T;
+    using C = typename SF::C;
     using L = Lat<DIM>;
     __shared__ double red[8][256];
+    __shared__ uint32_t bits[K2_MAXBOX / 32];
+    __shared__ int woff[K2_MAXBOX / 32 + 1];
+    __shared__ int cell[K2_MAXSHELL];
+    __shared__ T mom[DIM + 2][K2_MAXSHELL];       // rho - 1, j, S - T_ref per stencil node
+    __shared__ int s_total;
     const int p = blockIdx.x, tid = threadIdx.x;
     if (block_halted(a.lb.err)) return;
     const DevParticle P = a.part[p];
     const int m0 = a.mk_start[p], nm = a.mk_start[p + 1] - m0;
     const int t0 = a.tmpl_start[P.tmpl];
     const int nn[3] = {a.lb.nx, a.lb.ny, a.lb.nz};
+
+    // Stencil box: the cells floor(X_l) and floor(X_l) + 1 of every point.
+    const double re = a.tmpl_rext[P.tmpl];
+    int bo[3] = {0, 0, 0}, bs[3] = {1, 1, 1};
+    for (int d = 0; d < DIM; ++d) {
+        bo[d] = (int)floor(P.x[d] - re);
+        bs[d] = (int)floor(P.x[d] + re) + 2 - bo[d];
+    }
+    const int nbox = bs[0] * bs[1] * bs[2];
+    const int nwords = (nbox + 31) / 32;
+    bool boxed = nbox > 0 && nbox <= K2_MAXBOX;
+
+    // --- 1. mark the stencil nodes, 2. compact them, 3. moments per node ---
+    if (boxed) {
+        for (int w = tid; w < nwords; w += 256) bits[w] = 0u;
+        __syncthreads();
+        for (int m = tid; m < nm; m += 256) {
+            const double4 r4 = a.tmpl[t0 + m];
+            const double r[3] = {r4.x, r4.y, r4.z};
+            int u[3] = {0, 0, 0};
+            for (int d = 0; d < DIM; ++d) u[d] = (int)floor(P.x[d] + r[d]) - bo[d];
+            for (int c = 0; c < (1 << DIM); ++c) {
+                const int cx = u[0] + (c & 1), cy = u[1] + ((c >> 1) & 1), cz = u[2] + ((c >> 2) & 1);
+                const int lin = (cz * bs[1] + cy) * bs[0] + cx;
+                atomicOr(&bits[lin >> 5], 1u << (lin & 31));
+            }
+        }
+        __syncthreads();
+        // exclusive scan of the per-word counts (Hillis-Steele over 256 partial sums)
+        const int per = (nwords + 255) / 256;
+        int local = 0;
+        for (int w = tid * per; w < min(nwords, (tid + 1) * per); ++w) local += __popc(bits[w]);
+        red[0][tid] = (double)local;
+        __syncthreads();
+        for (int off = 1; off < 256; off <<= 1) {
+            const double v = tid >= off ? red[0][tid - off] : 0.0;
+            __syncthreads();
+            red[0][tid] += v;
+            __syncthreads();
+        }
+        int run = tid == 0 ? 0 : (int)red[0][tid - 1];
+        for (int w = tid * per; w < min(nwords, (tid + 1) * per); ++w) {
+            woff[w] = run;
+            run += __popc(bits[w]);
+        }
+        if (tid == 255) s_total = (int)red[0][255];
+        __syncthreads();
+        boxed = s_total <= K2_MAXSHELL;            // uniform
+        if (boxed) {
+            for (int w = tid; w < nwords; w += 256) {
+                uint32_t b = bits[w];
+                int k = woff[w];
+                while (b) {
+                    const int bit = __ffs(b) - 1;
+                    b &= b - 1;
+                    cell[k++] = w * 32 + bit;
+                }
+            }
+            __syncthreads();
+            const int total = s_total;
+            for (int k = tid; k < total; k += 256) {
+                const int lin = cell[k];
+                int ix[3];
+                ix[0] = lin % bs[0];
+                ix[1] = (lin / bs[0]) % bs[1];
+                ix[2] = lin / (bs[0] * bs[1]);
+                for (int d = 0; d < 3; ++d) ix[d] = d < DIM ? clamp_or_wrap(bo[d] + ix[d], nn[d], a.lb.per[d]) : 0;
+                T f[L::Q];
+                C g[L::QG];
+                pull<DIM, SF, T, C>(a.lb, ix[0], ix[1], ix[2], f, g);
+                C drho, j[3], dS;
+                moments<DIM, C>(f, g, drho, j, dS);
+                mom[0][k] = (T)drho;
+#pragma unroll
+                for (int d = 0; d < DIM; ++d) mom[1 + d][k] = (T)j[d];
+                mom[DIM + 1][k] = (T)dS;
+            }
+            __syncthreads();
+        }
+    }
+
+    // --- 4. interpolation (Eq. lbm6, i_max = 2), exchange, records, reactions ---
     double s[8] = {0, 0, 0, 0, 0, 0, 0, 0};
     for (int m = tid; m < nm; m += 256) {
-        const double4 r4 = a.tmpl[t0 + m];
-        const double r[3] = {r4.x, r4.y, DIM == 3 ? r4.z : 0.0};
-        const double A = r4.w;
-        double X[3], U[3];
-        U[0] = P.u[0] + (P.om[1] * r[2] - P.om[2] * r[1]);
-        U[1] = P.u[1] + (P.om[2] * r[0] - P.om[0] * r[2]);
-        U[2] = DIM == 3 ? P.u[2] + (P.om[0] * r[1] - P.om[1] * r[0]) : 0.0;
+        double r[3], U[3], tt[3];
         MarkerRec<T> rec;
-        rec.pad = 0;
-        int cb[3][2];
-        T tt[3];
-#pragma unroll
-        for (int d = 0; d < 3; ++d) {
-            if (d < DIM) {
-                X[d] = P.x[d] + r[d];
-                const double fl = floor(X[d]);
-                rec.b[d] = (int)fl;
-                tt[d] = (T)(X[d] - fl);
-                cb[d][0] = clamp_or_wrap(rec.b[d], nn[d], a.lb.per[d]);
-                cb[d][1] = clamp_or_wrap(rec.b[d] + 1, nn[d], a.lb.per[d]);
-            } else {
-                X[d] = 0; rec.b[d] = 0; tt[d] = 0; cb[d][0] = cb[d][1] = 0;
-            }
-            rec.t[d] = tt[d];
-        }
+        marker_setup<DIM, T>(P, a.tmpl[t0 + m], r, U, rec, tt);
+        const double A = a.tmpl[t0 + m].w;
         // The interpolation and the exchange are formed in FP64 whatever the
         // storage: near a steady state T_p - T_l and rho_l U_l - j_l are small
         // differences of O(1) numbers, and their rounding would act as a
@@ -611,23 +771,34 @@ __global__ __launch_bounds__(256) void k_markers(MkArgs<typename SF::T> a)
 #pragma unroll 1
         for (int c = 0; c < (1 << DIM); ++c) {
             double W = 1;
-            int ix[3];
+            int o[3] = {c & 1, (c >> 1) & 1, (c >> 2) & 1};
 #pragma unroll
-            for (int d = 0; d < 3; ++d) {
-                const int o = (c >> d) & 1;
-                ix[d] = d < DIM ? cb[d][o] : 0;
-                if (d < DIM) W *= o ? tt[d] : 1.0 - tt[d];
+            for (int d = 0; d < DIM; ++d) W *= o[d] ? tt[d] : 1.0 - tt[d];
+            double v[DIM + 2];
+            if (boxed) {
+                int u[3] = {0, 0, 0};
+                for (int d = 0; d < DIM; ++d) u[d] = rec.b[d] + o[d] - bo[d];
+                const int lin = (u[2] * bs[1] + u[1]) * bs[0] + u[0];
+                const int k = woff[lin >> 5] + __popc(bits[lin >> 5] & ((1u << (lin & 31)) - 1u));
+#pragma unroll
+                for (int q = 0; q < DIM + 2; ++q) v[q] = (double)mom[q][k];
+            } else {
+                int ix[3] = {0, 0, 0};
+                for (int d = 0; d < DIM; ++d) ix[d] = clamp_or_wrap(rec.b[d] + o[d], nn[d], a.lb.per[d]);
+                T f[L::Q];
+                C g[L::QG];
+                pull<DIM, SF, T, C>(a.lb, ix[0], ix[1], ix[2], f, g);
+                C drho, j[3], dS;
+                moments<DIM, C>(f, g, drho, j, dS);
+                v[0] = (double)drho;
+#pragma unroll
+                for (int d = 0; d < DIM; ++d) v[1 + d] = (double)j[d];
+                v[DIM + 1] = (double)dS;
             }
-            using C = typename SF::C;
-            T f[L::Q];
-            C g[L::QG];
-            pull<DIM, SF, T, C>(a.lb, ix[0], ix[1], ix[2], f, g);
-            C drho, j[3], dS;
-            moments<DIM, C>(f, g, drho, j, dS);
-            rl += W * (double)drho;
+            rl += W * v[0];
 #pragma unroll
-            for (int d = 0; d < 3; ++d) jl[d] += W * (double)j[d];
-            sl += W * (double)dS;
+            for (int d = 0; d < DIM; ++d) jl[d] += W * v[1 + d];
+            sl += W * v[DIM + 1];
         }
         const double rho_l = 1.0 + rl;
         const double dTl = (P.T - a.Tref) - sl;          // T_p - T_l
@@ -648,6 +819,7 @@ __global__ __launch_bounds__(256) void k_markers(MkArgs<typename SF::T> a)
         s[7] += dTl * A;
     }
     if (!a.react) return;
+    __syncthreads();
 #pragma unroll
     for (int k = 0; k < 8; ++k) red[k][tid] = s[k];
     __syncthreads();
@@ -764,6 +936,21 @@ __global__ __launch_bounds__(1024) void k_scan(const int *count, int *start, int
         if (fill) fill[i] = 0;
     }
     if (tid == 1023) start[n] = part[1023];
+}
+
+// Each tile's particle list in ascending order (the scatter fills it in
+// arrival order), so that K1 sums its markers in a reproducible order.
+__global__ void k_sort_lists(const int *start, int *items, int n)
+{
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= n) return;
+    const int b = start[t], e = start[t + 1];
+    for (int i = b + 1; i < e; ++i) {
+        const int v = items[i];
+        int j = i - 1;
+        while (j >= b && items[j] > v) { items[j + 1] = items[j]; --j; }
+        items[j + 1] = v;
+    }
 }
 
 // --------------------------------------------------------------------------
