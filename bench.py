@@ -90,6 +90,30 @@ def time_gpu(cfg, P, storage, steps, warmup, profile):
     return out
 
 
+def copy_probe(nbytes=1 << 30, reps=10):
+    """A plain device copy of known size (one elementwise kernel: every byte
+    read once and written once).  Gives the box's achievable copy bandwidth
+    and, under rocprofv3 --pmc, the scale of the FETCH_SIZE / WRITE_SIZE
+    counters."""
+    import torch
+
+    src = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    torch.neg(src, out=dst)
+    torch.cuda.synchronize()
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    ev0.record()
+    for _ in range(reps):
+        torch.neg(src, out=dst)
+    ev1.record()
+    torch.cuda.synchronize()
+    ms = ev0.elapsed_time(ev1) / reps
+    del src, dst
+    torch.cuda.empty_cache()
+    return dict(bytes_per_launch=2 * nbytes, ms=round(ms, 4), GBs=round(2 * nbytes / (ms * 1e-3) / 1e9, 1))
+
+
 def cpu_baseline(cfg, P, steps):
     from oracle import oracle as O
 
@@ -118,6 +142,7 @@ def main() -> int:
     ap.add_argument("--cpu-steps", type=int, default=2)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--empty", action="store_true", help="analysis: the same lattice without particles")
+    ap.add_argument("--no-copy-probe", action="store_true")
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
@@ -184,6 +209,8 @@ def main() -> int:
         "phase_ms_per_step": phases,
         "variants": variants,
     }
+    if not args.no_copy_probe:
+        line["device_copy"] = copy_probe()
     if not args.no_cpu:
         line["cpu_baseline"] = cpu_baseline(cfg, P, args.cpu_steps)
     print(json.dumps(line), flush=True)

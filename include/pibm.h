@@ -43,9 +43,12 @@ typedef enum {
 } pibm_status;
 
 /* Storage of the distributions.  Every variant stores deviations from the
- * rest state (f - w rho0, g - w T_ref) and collides in the compute type:
- * F32 stores and computes in float, F64 in double, F16DEV / BF16DEV store
- * 16-bit deviations scaled by 1/w and compute in float. */
+ * rest state (f - w rho0, g - w T_ref) and collides in a compute type:
+ * F32 stores float and collides in double, rounding the stored deviations
+ * stochastically (a counter hash of node, population and step decides the
+ * rounding direction, so runs are reproducible); F64 stores and collides in
+ * double; F16DEV / BF16DEV store 16-bit deviations scaled by 1/w, collide in
+ * float and round stochastically the same way. */
 typedef enum {
     PIBM_STORE_F32 = 0,
     PIBM_STORE_F64 = 1,

@@ -178,8 +178,14 @@ int make_plan(const pibm_params *p, const pibm_particle *pt, int np, Plan &P)
     P.mk_start.assign(np + 1, 0);
     P.ntmpl_mk = 0;
     for (auto &t : P.tmpls) P.ntmpl_mk += (long long)t.off.size() / 4;
-    for (int i = 0; i < np; ++i) P.mk_start[i + 1] = P.mk_start[i] + (int)(P.tmpls[P.ptmpl[i]].off.size() / 4);
-    P.nmk = P.mk_start[np];
+    long long nmk = 0;
+    for (int i = 0; i < np; ++i) {
+        nmk += (long long)(P.tmpls[P.ptmpl[i]].off.size() / 4);
+        // the spreading queue packs a point index in 27 bits
+        if (nmk >= (1LL << 27)) return PIBM_EINVAL;
+        P.mk_start[i + 1] = (int)nmk;
+    }
+    P.nmk = nmk;
     // tile-list capacity: every tile a particle's footprint can touch
     P.tile_cap = 0;
     for (int i = 0; i < np; ++i) {

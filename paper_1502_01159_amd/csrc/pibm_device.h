@@ -371,25 +371,65 @@ __device__ __forceinline__ int wrap_or_out(int c, int n, int per)
 // K1: fused pull-stream + moments + PIBM spreading (Eqs. lbm10-lbm12,
 // lbm12.6) + buoyancy + Guo-forced BGK for f (lbm2, lbm3, lbm9) and
 // source-forced BGK for g (lbm2.5, lbm12.5).  One workgroup per 1024-node
-// tile.  Spreading: each wave tests 64 markers at a time against the tile
-// and, for every hit, lays the marker's 4^d footprint across its lanes (one
-// node per lane) and adds into its own LDS copy of the tile's force and heat
-// (plain read-add-write: no two lanes share a node, and one wave's LDS
-// operations complete in order); the copies are summed in a fixed order, so
-// with the tile lists sorted the result is reproducible bit for bit.  Nothing
-// of it is written to HBM.
+// tile; nothing of the spreading is written to HBM.
+//
+// Spreading in three steps per wave: (1) each lane tests one Lagrangian
+// point of the tile's particle list against the tile and counts the rows
+// (fixed y, z) of its 4^d footprint that lie in the tile; (2) a wave prefix
+// sum appends one (point, row) entry per such row to the wave's LDS queue;
+// (3) whenever 64 entries are queued, each lane takes one and adds the
+// row's four nodes into the tile's accumulators.  The accumulators are
+// 64-bit fixed point (see SpreadFix): integer addition does not depend on order,
+// so the result is the same bit for bit whatever the interleaving of lanes,
+// waves and list entries, with no atomics on floating point.
 // --------------------------------------------------------------------------
-// Value of `v` in lane `k` (wave-uniform k), through the scalar unit.
-__device__ __forceinline__ float lane_bcast(float v, int k)
+// Fixed-point format of the spreading accumulators per point-record type.
+// FP32 records (FP32 / 16-bit storage): 2^-42 resolution, contributions
+// clamped to |v| <= 256 and rounded to nearest with the 1.5 * 2^52 shifter
+// (the integer lands in the low mantissa bits).  FP64 records (the parity
+// path): 2^-50 resolution, |v| <= 64, exact round-to-nearest conversion.
+// Either way a node holds thousands of maximal contributions before the
+// int64 sum could overflow; the clamp also maps NaN to a finite value, which
+// the node's velocity check then flags.
+template <class T> struct SpreadFix;
+template <> struct SpreadFix<float> {
+    static constexpr float SCALE = 0x1p42f, LIM = 256.0f;
+    static constexpr double INV = 0x1p-42;
+    static __device__ __forceinline__ unsigned long long fix(float scaled)
+    {
+        const double sh = 0x1.8p52;
+        return (unsigned long long)(__double_as_longlong((double)scaled + sh) - __double_as_longlong(sh));
+    }
+};
+template <> struct SpreadFix<double> {
+    static constexpr double SCALE = 0x1p50, LIM = 64.0;
+    static constexpr double INV = 0x1p-50;
+    static __device__ __forceinline__ unsigned long long fix(double scaled)
+    {
+        return (unsigned long long)(long long)rint(scaled);
+    }
+};
+
+// Node index on one axis: wrapped on periodic axes, unchanged otherwise (a
+// node outside the domain never lies in a tile's interior range, or lies in
+// a ragged tile's padding, which the node phase skips).
+__device__ __forceinline__ int spread_axis(int c, int n, int per)
 {
-    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), k));
+    if (per) { c %= n; if (c < 0) c += n; }
+    return c;
 }
-__device__ __forceinline__ double lane_bcast(double v, int k)
+// Exclusive prefix sum over the wave of cnt (0 <= cnt < 32) and the total.
+__device__ __forceinline__ int wave_prefix5(int cnt, int &total)
 {
-    const long long b = __double_as_longlong(v);
-    const int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffffll), k);
-    const int hi = __builtin_amdgcn_readlane((int)(b >> 32), k);
-    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+    int pre = 0, tot = 0;
+#pragma unroll
+    for (int bit = 0; bit < 5; ++bit) {
+        const unsigned long long bm = __ballot((cnt >> bit) & 1);
+        pre += (int)__builtin_amdgcn_mbcnt_hi((unsigned)(bm >> 32), __builtin_amdgcn_mbcnt_lo((unsigned)bm, 0u)) << bit;
+        tot += __popcll(bm) << bit;
+    }
+    total = tot;
+    return pre;
 }
 
 constexpr int XCD_CHUNK = 8;
@@ -402,14 +442,6 @@ __device__ __forceinline__ int xcd_tile(int b, int G)
     return (slot / XCD_CHUNK) * span + xcd * XCD_CHUNK + slot % XCD_CHUNK;
 }
 
-template <int DIM, class SF> struct SpreadLds {
-    using T = typename SF::T;
-    static constexpr int NC = DIM + 1;
-    // one copy per wave for 4-byte accumulators; one shared copy (LDS atomics,
-    // summation order not fixed) for the FP64 parity path
-    static constexpr int NCOPY = sizeof(T) == 4 ? LBM_THREADS / 64 : 1;
-};
-
 template <int DIM, class SF, bool MACRO>
 __global__ __launch_bounds__(LBM_THREADS) void k_lbm(LbmArgs<typename SF::T> a)
 {
@@ -417,8 +449,10 @@ __global__ __launch_bounds__(LBM_THREADS) void k_lbm(LbmArgs<typename SF::T> a)
     using L = Lat<DIM>;
     using TL = Tile<DIM>;
     constexpr int NC = DIM + 1;
-    constexpr int NCOPY = SpreadLds<DIM, SF>::NCOPY;
-    __shared__ T acc[NCOPY][NC][TL::NPAD];
+    constexpr int RMAX = DIM == 3 ? 16 : 4;          // footprint rows per point
+    constexpr int QCAP = 64 * RMAX + 64;
+    __shared__ unsigned long long acc[NC][TL::N];     // fixed-point F_B, Q_B per tile node
+    __shared__ int queue[LBM_THREADS / 64][QCAP];
 
     // XCD-aware order: consecutive workgroups go to different XCDs (round
     // robin over 8); give each XCD runs of XCD_CHUNK consecutive tiles so that
@@ -433,75 +467,101 @@ __global__ __launch_bounds__(LBM_THREADS) void k_lbm(LbmArgs<typename SF::T> a)
     const int ps = a.tile_start[t], pe = a.tile_start[t + 1];
     const bool has = pe > ps;
     if (has) {
-        for (int i = tid; i < NCOPY * NC * TL::NPAD; i += LBM_THREADS) (&acc[0][0][0])[i] = (T)0;
+        for (int i = tid; i < NC * TL::N; i += LBM_THREADS) (&acc[0][0])[i] = 0ull;
         __syncthreads();
         const int lane = tid & 63, wv = tid >> 6;
-        const int cp = NCOPY == 1 ? 0 : wv;
-        const int org[3] = {x0, y0, z0};
-        const int ext[3] = {TL::X, TL::Y, TL::Z};
-        const int nn[3] = {a.nx, a.ny, a.nz};
-        // this lane's offset inside a marker footprint
-        const int kxyz[3] = {lane & 3, (lane >> 2) & 3, DIM == 3 ? (lane >> 4) : 0};
-        const bool lane_on = DIM == 3 || lane < 16;
-        for (int e = ps; e < pe; ++e) {
-            const int p = a.tile_items[e];
-            const int m0 = a.mk_start[p], m1 = a.mk_start[p + 1];
-            for (int base = m0 + wv * 64; base < m1; base += LBM_THREADS) {
-                const int m = base + lane;
-                bool hit = m < m1;
-                MarkerRec<T> rec;
-                if (hit) {
-                    rec = a.mk[m];
+        int *q = queue[wv];
+        int qn = 0;                                   // wave-uniform queue length
+
+        // (3) one queued (point, row) entry per lane: the row's nodes x = b-1 .. b+2
+        auto drain = [&](int code) {
+            const int m = code >> 4, ky = (code >> 2) & 3, kz = code & 3;
+            const MarkerRec<T> &r = a.mk[m];
+            const int ly = spread_axis(r.b[1] - 1 + ky, a.ny, a.per[1]) - y0;
+            const int lz = DIM == 3 ? spread_axis(r.b[2] - 1 + kz, a.nz, a.per[2]) - z0 : 0;
+            const int row = TL::X * (ly + TL::Y * lz);
+            const T wyz = DIM == 3 ? r.w[1][ky] * r.w[2][kz] : r.w[1][ky];
+            T v[NC];
 #pragma unroll
-                    for (int d = 0; d < DIM; ++d) {
-                        bool any = false;
+            for (int c = 0; c < NC; ++c) {
+                const T raw = c < DIM ? r.fa[c] : r.qa;
+                const T cl = fmin(fmax(raw, -SpreadFix<T>::LIM), SpreadFix<T>::LIM);   // NaN -> -limit
+                v[c] = cl * SpreadFix<T>::SCALE * wyz;
+            }
+            const int bx = r.b[0];
+#pragma unroll
+            for (int kx = 0; kx < 4; ++kx) {
+                const int lx = spread_axis(bx - 1 + kx, a.nx, a.per[0]) - x0;
+                if (lx >= 0 && lx < TL::X) {
+                    const T wx = r.w[0][kx];
+#pragma unroll
+                    for (int c = 0; c < NC; ++c) atomicAdd(&acc[c][row + lx], SpreadFix<T>::fix(v[c] * wx));
+                }
+            }
+        };
+
+        int chunk = 0;                                // tile-wide chunk counter: balances the waves
+        for (int e0 = ps; e0 < pe; e0 += 64) {
+            // the next 64 list entries, loaded in parallel and broadcast below
+            int pm0 = 0, pm1 = 0;
+            if (e0 + lane < pe) {
+                const int p = a.tile_items[e0 + lane];
+                pm0 = a.mk_start[p];
+                pm1 = a.mk_start[p + 1];
+            }
+            const int ne = min(64, pe - e0);
+            for (int e = 0; e < ne; ++e) {
+                const int m0 = __builtin_amdgcn_readlane(pm0, e), m1 = __builtin_amdgcn_readlane(pm1, e);
+                const int nch = (m1 - m0 + 63) >> 6;
+                // chunks of this particle handled by this wave: j = chunk + j' with j % 4 == wv
+                int j = (wv - chunk) & 3;
+                chunk += nch;
+                for (; j < nch; j += LBM_THREADS / 64) {
+                    const int m = m0 + 64 * j + lane;
+                    int cnt = 0, ymask = 0, zmask = 1;
+                    if (m < m1) {
+                        const int4 b4 = *(const int4 *)&a.mk[m].b[0];
+                        bool xin = false;
+                        ymask = 0;
 #pragma unroll
                         for (int k = 0; k < 4; ++k) {
-                            const int l = wrap_or_out(rec.b[d] - 1 + k, nn[d], a.per[d]) - org[d];
-                            any = any || (l >= 0 && l < ext[d]);
+                            const int lx = spread_axis(b4.x - 1 + k, a.nx, a.per[0]) - x0;
+                            xin = xin || (lx >= 0 && lx < TL::X);
+                            const int ly = spread_axis(b4.y - 1 + k, a.ny, a.per[1]) - y0;
+                            ymask |= (ly >= 0 && ly < TL::Y) ? (1 << k) : 0;
                         }
-                        hit = hit && any;
-                    }
-                }
-                unsigned long long mask = __ballot(hit);
-                while (mask) {
-                    // the hit lane's record, broadcast to the whole wave
-                    const int k = __ffsll((unsigned long long)mask) - 1;
-                    mask &= mask - 1;
-                    int loc = 0;
-                    bool in = lane_on;
-                    T W = (T)1;
+                        if (DIM == 3) {
+                            zmask = 0;
 #pragma unroll
-                    for (int d = 0; d < DIM; ++d) {
-                        const int bd = __builtin_amdgcn_readlane(rec.b[d], k);
-                        const int l = wrap_or_out(bd - 1 + kxyz[d], nn[d], a.per[d]) - org[d];
-                        in = in && l >= 0 && l < ext[d];
-                        loc += (d == 0 ? l : (d == 1 ? TL::PY * l : TL::PZ * l));
-                        const T w0 = lane_bcast(rec.w[d][0], k), w1 = lane_bcast(rec.w[d][1], k);
-                        const T w2 = lane_bcast(rec.w[d][2], k), w3 = lane_bcast(rec.w[d][3], k);
-                        const int kk = kxyz[d];
-                        W *= kk == 0 ? w0 : (kk == 1 ? w1 : (kk == 2 ? w2 : w3));
-                    }
-                    T fa[DIM], qa;
-#pragma unroll
-                    for (int c = 0; c < DIM; ++c) fa[c] = lane_bcast(rec.fa[c], k);
-                    qa = lane_bcast(rec.qa, k);
-                    if (in) {
-                        if (NCOPY > 1) {
-                            // private copy of this wave, distinct node per lane:
-                            // a plain read-add-write (LDS atomics run lane by lane)
-#pragma unroll
-                            for (int c = 0; c < DIM; ++c) acc[cp][c][loc] += fa[c] * W;
-                            acc[cp][DIM][loc] += qa * W;
-                        } else {
-#pragma unroll
-                            for (int c = 0; c < DIM; ++c) atomicAdd(&acc[cp][c][loc], fa[c] * W);
-                            atomicAdd(&acc[cp][DIM][loc], qa * W);
+                            for (int k = 0; k < 4; ++k) {
+                                const int lz = spread_axis(b4.z - 1 + k, a.nz, a.per[2]) - z0;
+                                zmask |= (lz >= 0 && lz < TL::Z) ? (1 << k) : 0;
+                            }
                         }
+                        cnt = xin ? __popc(ymask) * __popc(zmask) : 0;
+                    }
+                    // (2) append this lane's rows to the wave's queue
+                    int tot;
+                    int pos = qn + wave_prefix5(cnt, tot);
+                    if (cnt) {
+#pragma unroll
+                        for (int ky = 0; ky < 4; ++ky)
+#pragma unroll
+                            for (int kz = 0; kz < (DIM == 3 ? 4 : 1); ++kz)
+                                if (((ymask >> ky) & (zmask >> kz) & 1) != 0) q[pos++] = (m << 4) | (ky << 2) | kz;
+                    }
+                    qn += tot;
+                    __builtin_amdgcn_wave_barrier();
+                    while (qn >= 64) {
+                        qn -= 64;
+                        const int code = q[qn + lane];
+                        __builtin_amdgcn_wave_barrier();
+                        drain(code);
                     }
                 }
             }
         }
+        if (lane < qn) drain(q[lane]);
         __syncthreads();
     }
 
@@ -521,14 +581,11 @@ __global__ __launch_bounds__(LBM_THREADS) void k_lbm(LbmArgs<typename SF::T> a)
         C FB[3] = {0, 0, 0};
         C QB = 0;
         if (has) {
-            const int li = TL::lds(lx, ly, lz);
 #pragma unroll
             for (int c = 0; c < NC; ++c) {
-                T v = acc[0][c][li];
-#pragma unroll
-                for (int w = 1; w < NCOPY; ++w) v += acc[w][c][li];   // fixed order
-                if (c < DIM) FB[c] = (C)v;
-                else QB = (C)v;
+                const C v = (C)((double)(long long)acc[c][ln] * SpreadFix<T>::INV);
+                if (c < DIM) FB[c] = v;
+                else QB = v;
             }
         }
         T f[L::Q];
