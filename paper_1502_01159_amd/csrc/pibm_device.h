@@ -450,7 +450,8 @@ __global__ __launch_bounds__(LBM_THREADS) void k_lbm(LbmArgs<typename SF::T> a)
     using TL = Tile<DIM>;
     constexpr int NC = DIM + 1;
     constexpr int RMAX = DIM == 3 ? 16 : 4;          // footprint rows per point
-    constexpr int QCAP = 64 * RMAX + 64;
+    constexpr int QCAP = 128 + 64 * RMAX;            // < 128 queued before each append
+    constexpr int KSCAN = 4;                          // chunks whose loads are in flight together
     __shared__ unsigned long long acc[NC][TL::N];     // fixed-point F_B, Q_B per tile node
     __shared__ int queue[LBM_THREADS / 64][QCAP];
 
@@ -467,101 +468,155 @@ __global__ __launch_bounds__(LBM_THREADS) void k_lbm(LbmArgs<typename SF::T> a)
     const int ps = a.tile_start[t], pe = a.tile_start[t + 1];
     const bool has = pe > ps;
     if (has) {
+        const int lane = tid & 63, wv = tid >> 6;
+        // the first 64 entries of the tile's particle list, loaded while the
+        // accumulators are cleared
+        int pm0 = 0, pn = 0;
+        if (lane < pe - ps) {
+            const int p = a.tile_items[ps + lane];
+            pm0 = a.mk_start[p];
+            pn = a.mk_start[p + 1] - pm0;
+        }
         for (int i = tid; i < NC * TL::N; i += LBM_THREADS) (&acc[0][0])[i] = 0ull;
         __syncthreads();
-        const int lane = tid & 63, wv = tid >> 6;
         int *q = queue[wv];
         int qn = 0;                                   // wave-uniform queue length
 
-        // (3) one queued (point, row) entry per lane: the row's nodes x = b-1 .. b+2
-        auto drain = [&](int code) {
-            const int m = code >> 4, ky = (code >> 2) & 3, kz = code & 3;
-            const MarkerRec<T> &r = a.mk[m];
-            const int ly = spread_axis(r.b[1] - 1 + ky, a.ny, a.per[1]) - y0;
-            const int lz = DIM == 3 ? spread_axis(r.b[2] - 1 + kz, a.nz, a.per[2]) - z0 : 0;
+        // (3) a queued (point, row) entry: the row's nodes x = b-1 .. b+2.
+        // fetch() only issues the loads, so that two batches are in flight
+        // together; apply() adds the contributions.
+        struct Row { int4 b; T w0[4]; T wy, wz; T f[NC]; int ky, kz; };
+        auto fetch = [&](int code, Row &r) {
+            const int m = code >> 4;
+            r.ky = (code >> 2) & 3;
+            r.kz = code & 3;
+            const MarkerRec<T> *R = a.mk + m;
+            r.b = *(const int4 *)&R->b[0];
+#pragma unroll
+            for (int k = 0; k < 4; ++k) r.w0[k] = R->w[0][k];
+            r.wy = R->w[1][r.ky];
+            r.wz = DIM == 3 ? R->w[2][r.kz] : (T)1;
+#pragma unroll
+            for (int c = 0; c < NC; ++c) r.f[c] = c < DIM ? R->fa[c] : R->qa;
+        };
+        auto apply = [&](const Row &r) {
+            const int ly = spread_axis(r.b.y - 1 + r.ky, a.ny, a.per[1]) - y0;
+            const int lz = DIM == 3 ? spread_axis(r.b.z - 1 + r.kz, a.nz, a.per[2]) - z0 : 0;
             const int row = TL::X * (ly + TL::Y * lz);
-            const T wyz = DIM == 3 ? r.w[1][ky] * r.w[2][kz] : r.w[1][ky];
+            const T wyz = r.wy * r.wz;
             T v[NC];
 #pragma unroll
             for (int c = 0; c < NC; ++c) {
-                const T raw = c < DIM ? r.fa[c] : r.qa;
-                const T cl = fmin(fmax(raw, -SpreadFix<T>::LIM), SpreadFix<T>::LIM);   // NaN -> -limit
+                const T cl = fmin(fmax(r.f[c], -SpreadFix<T>::LIM), SpreadFix<T>::LIM);   // NaN -> -limit
                 v[c] = cl * SpreadFix<T>::SCALE * wyz;
             }
-            const int bx = r.b[0];
 #pragma unroll
             for (int kx = 0; kx < 4; ++kx) {
-                const int lx = spread_axis(bx - 1 + kx, a.nx, a.per[0]) - x0;
+                const int lx = spread_axis(r.b.x - 1 + kx, a.nx, a.per[0]) - x0;
                 if (lx >= 0 && lx < TL::X) {
-                    const T wx = r.w[0][kx];
 #pragma unroll
-                    for (int c = 0; c < NC; ++c) atomicAdd(&acc[c][row + lx], SpreadFix<T>::fix(v[c] * wx));
+                    for (int c = 0; c < NC; ++c) atomicAdd(&acc[c][row + lx], SpreadFix<T>::fix(v[c] * r.w0[kx]));
                 }
             }
         };
-
-        int chunk = 0;                                // tile-wide chunk counter: balances the waves
-        for (int e0 = ps; e0 < pe; e0 += 64) {
-            // the next 64 list entries, loaded in parallel and broadcast below
-            int pm0 = 0, pm1 = 0;
-            if (e0 + lane < pe) {
-                const int p = a.tile_items[e0 + lane];
-                pm0 = a.mk_start[p];
-                pm1 = a.mk_start[p + 1];
-            }
-            const int ne = min(64, pe - e0);
-            for (int e = 0; e < ne; ++e) {
-                const int m0 = __builtin_amdgcn_readlane(pm0, e), m1 = __builtin_amdgcn_readlane(pm1, e);
-                const int nch = (m1 - m0 + 63) >> 6;
-                // chunks of this particle handled by this wave: j = chunk + j' with j % 4 == wv
-                int j = (wv - chunk) & 3;
-                chunk += nch;
-                for (; j < nch; j += LBM_THREADS / 64) {
-                    const int m = m0 + 64 * j + lane;
-                    int cnt = 0, ymask = 0, zmask = 1;
-                    if (m < m1) {
-                        const int4 b4 = *(const int4 *)&a.mk[m].b[0];
-                        bool xin = false;
-                        ymask = 0;
+        auto drain2 = [&](int ca, bool va, int cb, bool vb) {
+            Row ra, rb;
+            if (va) fetch(ca, ra);
+            if (vb) fetch(cb, rb);
+            if (va) apply(ra);
+            if (vb) apply(rb);
+        };
+        // (1) + (2) for one point (m < 0: none) with base cell b
+        auto scan = [&](int m, int4 b) {
+            int cnt = 0, ymask = 0, zmask = 1;
+            if (m >= 0) {
+                bool xin = false;
 #pragma unroll
-                        for (int k = 0; k < 4; ++k) {
-                            const int lx = spread_axis(b4.x - 1 + k, a.nx, a.per[0]) - x0;
-                            xin = xin || (lx >= 0 && lx < TL::X);
-                            const int ly = spread_axis(b4.y - 1 + k, a.ny, a.per[1]) - y0;
-                            ymask |= (ly >= 0 && ly < TL::Y) ? (1 << k) : 0;
-                        }
-                        if (DIM == 3) {
-                            zmask = 0;
+                for (int k = 0; k < 4; ++k) {
+                    const int lx = spread_axis(b.x - 1 + k, a.nx, a.per[0]) - x0;
+                    xin = xin || (lx >= 0 && lx < TL::X);
+                    const int ly = spread_axis(b.y - 1 + k, a.ny, a.per[1]) - y0;
+                    ymask |= (ly >= 0 && ly < TL::Y) ? (1 << k) : 0;
+                }
+                if (DIM == 3) {
+                    zmask = 0;
 #pragma unroll
-                            for (int k = 0; k < 4; ++k) {
-                                const int lz = spread_axis(b4.z - 1 + k, a.nz, a.per[2]) - z0;
-                                zmask |= (lz >= 0 && lz < TL::Z) ? (1 << k) : 0;
-                            }
-                        }
-                        cnt = xin ? __popc(ymask) * __popc(zmask) : 0;
-                    }
-                    // (2) append this lane's rows to the wave's queue
-                    int tot;
-                    int pos = qn + wave_prefix5(cnt, tot);
-                    if (cnt) {
-#pragma unroll
-                        for (int ky = 0; ky < 4; ++ky)
-#pragma unroll
-                            for (int kz = 0; kz < (DIM == 3 ? 4 : 1); ++kz)
-                                if (((ymask >> ky) & (zmask >> kz) & 1) != 0) q[pos++] = (m << 4) | (ky << 2) | kz;
-                    }
-                    qn += tot;
-                    __builtin_amdgcn_wave_barrier();
-                    while (qn >= 64) {
-                        qn -= 64;
-                        const int code = q[qn + lane];
-                        __builtin_amdgcn_wave_barrier();
-                        drain(code);
+                    for (int k = 0; k < 4; ++k) {
+                        const int lz = spread_axis(b.z - 1 + k, a.nz, a.per[2]) - z0;
+                        zmask |= (lz >= 0 && lz < TL::Z) ? (1 << k) : 0;
                     }
                 }
+                cnt = xin ? __popc(ymask) * __popc(zmask) : 0;
             }
+            int tot;
+            int pos = qn + wave_prefix5(cnt, tot);
+            if (cnt) {
+#pragma unroll
+                for (int ky = 0; ky < 4; ++ky)
+#pragma unroll
+                    for (int kz = 0; kz < (DIM == 3 ? 4 : 1); ++kz)
+                        if (((ymask >> ky) & (zmask >> kz) & 1) != 0) q[pos++] = (m << 4) | (ky << 2) | kz;
+            }
+            qn += tot;
+            __builtin_amdgcn_wave_barrier();
+            while (qn >= 128) {
+                qn -= 128;
+                const int ca = q[qn + lane], cb = q[qn + 64 + lane];
+                __builtin_amdgcn_wave_barrier();
+                drain2(ca, true, cb, true);
+            }
+        };
+
+        // The list in batches of 64 particles; within a batch the points of
+        // all its particles form one virtual array, cut into chunks of 64
+        // that the waves take in turn (chunk0 carries the turn across
+        // batches), KSCAN chunks per wave at a time.
+        int chunk0 = 0;
+        for (int e0 = ps; e0 < pe; e0 += 64) {
+            const int ne = min(64, pe - e0);
+            if (e0 != ps) {
+                pm0 = 0; pn = 0;
+                if (lane < ne) {
+                    const int p = a.tile_items[e0 + lane];
+                    pm0 = a.mk_start[p];
+                    pn = a.mk_start[p + 1] - pm0;
+                }
+            }
+            int incl = pn;                            // inclusive prefix over the batch
+#pragma unroll
+            for (int d = 1; d < 64; d <<= 1) {
+                const int y = __shfl_up(incl, d);
+                if (lane >= d) incl += y;
+            }
+            const int pre = incl - pn;                // first virtual index of particle `lane`
+            const int tot_m = __shfl(incl, 63);
+            const int nchunk = (tot_m + 63) >> 6;
+            for (int c = (wv - chunk0) & 3; c < nchunk; c += 4 * KSCAN) {
+                int mm[KSCAN];
+                int4 bb[KSCAN];
+#pragma unroll
+                for (int i = 0; i < KSCAN; ++i) {
+                    const int v = 64 * (c + 4 * i) + lane;
+                    const int vs = min(v, tot_m - 1);
+                    // particle holding virtual index vs: the last e < ne with pre[e] <= vs
+                    int e = 0;
+#pragma unroll
+                    for (int st = 32; st; st >>= 1) {
+                        const int cand = e + st;
+                        const int pc = __shfl(pre, cand & 63);
+                        if (cand < ne && pc <= vs) e = cand;
+                    }
+                    const int m = __shfl(pm0, e) + vs - __shfl(pre, e);
+                    mm[i] = v < tot_m ? m : -1;
+                    bb[i] = make_int4(0, 0, 0, 0);
+                    if (v < tot_m) bb[i] = *(const int4 *)&a.mk[m].b[0];
+                }
+#pragma unroll
+                for (int i = 0; i < KSCAN; ++i) scan(mm[i], bb[i]);
+            }
+            chunk0 += nchunk;
         }
-        if (lane < qn) drain(q[lane]);
+        drain2(q[lane], lane < qn, q[64 + lane], 64 + lane < qn);
         __syncthreads();
     }
 
