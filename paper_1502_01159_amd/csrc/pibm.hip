@@ -147,6 +147,9 @@ int make_plan(const pibm_params *p, const pibm_particle *pt, int np, Plan &P)
     P.N = (long long)p->nx * p->ny * p->nz;
     P.Ns = (P.N + 63) / 64 * 64;
     P.ssize = p->storage == PIBM_STORE_F64 ? 8 : (p->storage == PIBM_STORE_F32 ? 4 : 2);
+    // the lattice kernel reaches both arrays of an opposite pair of
+    // populations from the pair's first array with 32-bit byte offsets
+    if ((double)(p->dim == 2 ? 3 : 2) * (double)P.Ns * (double)P.ssize >= 4294967296.0) return PIBM_EINVAL;
     P.tsize = p->storage == PIBM_STORE_F64 ? 8 : 4;
     P.TX = TILE_X;
     P.TY = p->dim == 3 ? Tile<3>::Y : Tile<2>::Y;
@@ -352,6 +355,7 @@ template <class T> LbmArgs<T> lbm_args(const pibm_ctx *c)
     a.err = (int *)c->r(R_ERR);
     a.macro = nullptr;
     a.step = (uint32_t)c->step;
+    a.seed = mix32((uint32_t)c->step * 0xc2b2ae3du + 0x85ebca77u);
     return a;
 }
 

@@ -73,106 +73,81 @@ __host__ __device__ __forceinline__ uint32_t mix32(uint32_t x)
     x ^= x >> 16;
     return x;
 }
-__device__ __forceinline__ float unit_hash(uint32_t n, uint32_t q, uint32_t step)
+// Sixteen random bits per stored value: one hash per node and step, and an
+// odd multiple of it per value (the high or low half of the product).
+__device__ __forceinline__ uint32_t node_seed(uint32_t n, uint32_t step_seed)
 {
-    const uint32_t h = mix32(n * 0x9e3779b1u ^ mix32(q * 0x85ebca77u + step * 0xc2b2ae3du));
-    return (float)(h >> 8) * (1.0f / 16777216.0f);
+    return mix32(n * 0x9e3779b1u ^ step_seed);
+}
+__device__ __forceinline__ uint32_t sr_bits(uint32_t seed, int k)
+{
+    // 24-bit product (full-rate multiply) of the seed with an odd constant
+    const uint32_t P = __umul24(seed, ((uint32_t)(2 * (k >> 1) + 1) * 0x9e3779b1u) & 0xffffffu);
+    return (k & 1) ? (P & 0xffffu) : (P >> 16);
 }
 
 // --------------------------------------------------------------------------
-// Storage traits: load a stored deviation as the compute type; store
-// old + increment.  FP32 and the 16-bit formats round the store
-// stochastically (up or down with probability set by the residual, from the
-// hash above), so that increments smaller than half an ulp of a slowly
-// changing population are kept on average instead of being discarded every
-// step; the hash makes it reproducible bit for bit.  `w` is the lattice
-// weight of the direction (16-bit formats store dev / w).
+// Storage traits: decode a stored deviation to T; store old + increment.
+// FP32 and the 16-bit formats round the store stochastically: random bits
+// are added below the kept mantissa and the rest is cut off, which rounds
+// the magnitude up with probability equal to the cut-off fraction (to 2^-16
+// of an ulp).  Increments smaller than half an ulp of a slowly changing
+// population are so kept on average instead of being discarded every step;
+// the hash makes it reproducible bit for bit.  `w` is the lattice weight of
+// the direction (16-bit formats store dev / w).
 // --------------------------------------------------------------------------
 struct StF32 {
     using S = float; using T = float; using C = double;
     static __device__ __forceinline__ T cvt(S v, double) { return v; }
-    static __device__ __forceinline__ T ld(const S *p, size_t i, double) { return p[i]; }
-    static __device__ __forceinline__ void st(S *p, size_t i, T v, double) { p[i] = v; }
-    template <class A, class I>
-    static __device__ __forceinline__ void st_sum(S *p, size_t i, A old, I inc, double, float u)
+    static __device__ __forceinline__ void st(S *p, T v, double) { *p = v; }
+    static __device__ __forceinline__ void st_sum(S *p, T old, C inc, double, uint32_t r16)
     {
-        const double s = (double)old + (double)inc;            // exact for float operands
-        float r = (float)s;
-        const double e = s - (double)r;                        // exact residual, |e| <= ulp/2
-        if (e != 0.0) {
-            const float r2 = nextafterf(r, e > 0.0 ? INFINITY : -INFINITY);
-            if ((double)u * fabs((double)r2 - (double)r) < fabs(e)) r = r2;
-        }
-        p[i] = r;
+        // double -> float keeps 24 of 53 mantissa bits: randomise the 29 cut
+        unsigned long long b = (unsigned long long)__double_as_longlong((double)old + inc);
+        b = (b + ((unsigned long long)r16 << 13)) & ~0x1fffffffull;
+        *p = (float)__longlong_as_double((long long)b);
     }
 };
 struct StF64 {
     using S = double; using T = double; using C = double;
     static __device__ __forceinline__ T cvt(S v, double) { return v; }
-    static __device__ __forceinline__ T ld(const S *p, size_t i, double) { return p[i]; }
-    static __device__ __forceinline__ void st(S *p, size_t i, T v, double) { p[i] = v; }
-    template <class A, class I>
-    static __device__ __forceinline__ void st_sum(S *p, size_t i, A old, I inc, double, float) { p[i] = (T)(old + inc); }
+    static __device__ __forceinline__ void st(S *p, T v, double) { *p = v; }
+    static __device__ __forceinline__ void st_sum(S *p, T old, C inc, double, uint32_t) { *p = old + inc; }
 };
-// Stochastic rounding of a float `s` to a 16-bit format whose value of a bit
-// pattern is dec(bits); `h` is the round-to-nearest pattern of s.  The
-// neighbour on the other side of s is taken with probability |s - dec(h)| /
-// |dec(h') - dec(h)|.
-template <class Dec>
-__device__ __forceinline__ uint16_t sr16(float s, uint16_t h, float u, Dec dec)
-{
-    const float v = dec(h);
-    const float e = s - v;
-    if (!(e != 0.0f) || !(fabsf(s) < 3.0e38f)) return h;
-    const bool up = e > 0.0f;                       // neighbour toward +inf ?
-    uint16_t h2;
-    if ((h & 0x7fffu) == 0) h2 = up ? 0x0001u : 0x8001u;
-    else if (!(h & 0x8000u)) h2 = up ? (uint16_t)(h + 1) : (uint16_t)(h - 1);
-    else h2 = up ? (uint16_t)(h - 1) : (uint16_t)(h + 1);
-    const float gap = fabsf(dec(h2) - v);
-    return (u * gap < fabsf(e)) ? h2 : h;
-}
-
 struct StF16 {
     using S = __half; using T = float; using C = float;
-    static __device__ __forceinline__ float dec(uint16_t b) { __half h; __builtin_memcpy(&h, &b, 2); return __half2float(h); }
-    static __device__ __forceinline__ uint16_t enc(float v) { __half h = __float2half_rn(v); uint16_t b; __builtin_memcpy(&b, &h, 2); return b; }
     static __device__ __forceinline__ T cvt(S v, double w) { return __half2float(v) * (float)w; }
-    static __device__ __forceinline__ T ld(const S *p, size_t i, double w) { return __half2float(p[i]) * (float)w; }
-    static __device__ __forceinline__ void st(S *p, size_t i, T v, double w) { p[i] = __float2half_rn(v * (float)(1.0 / w)); }
-    template <class A, class I>
-    static __device__ __forceinline__ void st_sum(S *p, size_t i, A old, I inc, double w, float u)
+    static __device__ __forceinline__ void st(S *p, T v, double w) { *p = __float2half_rn(v * (float)(1.0 / w)); }
+    static __device__ __forceinline__ void st_sum(S *p, T old, C inc, double w, uint32_t r16)
     {
-        const float s = (float)(old + inc) * (float)(1.0 / w);
-        const uint16_t b = sr16(s, enc(s), u, dec);
-        __half h;
-        __builtin_memcpy(&h, &b, 2);
-        p[i] = h;
+        // float -> half keeps 11 of 24 significant bits in the half's normal
+        // range: randomise the 13 cut, then the conversion is exact (below
+        // 2^-14 it rounds to nearest)
+        const float s = (old + inc) * (float)(1.0 / w);
+        const uint32_t b = (__float_as_uint(s) + (r16 >> 3)) & ~0x1fffu;
+        *p = __float2half_rn(__uint_as_float(b));
     }
 };
 struct StBF16 {
     using S = uint16_t; using T = float; using C = float;
     static __device__ __forceinline__ T cvt(S v, double w) { return __uint_as_float(((uint32_t)v) << 16) * (float)w; }
-    static __device__ __forceinline__ T ld(const S *p, size_t i, double w) {
-        return __uint_as_float(((uint32_t)p[i]) << 16) * (float)w;
-    }
-    static __device__ __forceinline__ void st(S *p, size_t i, T v, double w) {
-        float s = v * (float)(1.0 / w);
-        uint32_t u = __float_as_uint(s);
-        // round to nearest even; NaN stays NaN
-        uint32_t r = (u & 0x7fffffffu) > 0x7f800000u ? (u | 0x00400000u) : u + 0x7fffu + ((u >> 16) & 1u);
-        p[i] = (uint16_t)(r >> 16);
-    }
-    static __device__ __forceinline__ float dec(uint16_t b) { return __uint_as_float(((uint32_t)b) << 16); }
-    template <class A, class I>
-    static __device__ __forceinline__ void st_sum(S *p, size_t i, A old, I inc, double w, float u)
+    static __device__ __forceinline__ void st(S *p, T v, double w)
     {
-        const float s = (float)(old + inc) * (float)(1.0 / w);
-        uint32_t x = __float_as_uint(s);
-        const uint32_t r = (x & 0x7fffffffu) > 0x7f800000u ? (x | 0x00400000u) : x + 0x7fffu + ((x >> 16) & 1u);
-        p[i] = sr16(s, (uint16_t)(r >> 16), u, dec);
+        const uint32_t u = __float_as_uint(v * (float)(1.0 / w));
+        // round to nearest even; NaN stays NaN
+        const uint32_t r = (u & 0x7fffffffu) > 0x7f800000u ? (u | 0x00400000u) : u + 0x7fffu + ((u >> 16) & 1u);
+        *p = (uint16_t)(r >> 16);
+    }
+    static __device__ __forceinline__ void st_sum(S *p, T old, C inc, double w, uint32_t r16)
+    {
+        const float s = (old + inc) * (float)(1.0 / w);
+        const uint32_t u = __float_as_uint(s);
+        // NaN keeps a non-zero mantissa; otherwise randomise the 16 cut bits
+        const uint32_t r = (u & 0x7fffffffu) > 0x7f800000u ? (u | 0x00400000u) : u + r16;
+        *p = (uint16_t)(r >> 16);
     }
 };
+
 
 // --------------------------------------------------------------------------
 // Shared records.
@@ -245,7 +220,8 @@ template <typename T> struct LbmArgs {
     const MarkerRec<T> *mk;
     int *err;
     T *macro;                      // macro pass: rho, u[3], T at k * Ns + n
-    uint32_t step;                 // step counter (stochastic-rounding stream)
+    uint32_t step;                 // step counter
+    uint32_t seed;                 // hash of the step counter (stochastic-rounding stream)
 };
 
 // --------------------------------------------------------------------------
@@ -268,7 +244,20 @@ __device__ __forceinline__ void nbr_axis(int c, int n, int per, int &m, int &p, 
 // f and anti-bounce-back (Dirichlet wall temperature) for g.  Branch-free:
 // every direction loads from one selected address (the upstream node in its
 // own array, or this node in the opposite direction's array at a wall), so
-// all loads of a node are in flight together.
+// all loads of a node are in flight together.  Addresses are 32-bit byte
+// offsets from the first array of the direction's opposite pair (a
+// wave-uniform base), which the host bounds below 4 GiB.
+template <class S>
+__device__ __forceinline__ S load_at(const S *base, uint32_t elem)
+{
+    return *(const S *)((const char *)base + (uint32_t)(elem * (uint32_t)sizeof(S)));
+}
+template <class S>
+__device__ __forceinline__ S *addr_at(S *base, uint32_t elem)
+{
+    return (S *)((char *)base + (uint32_t)(elem * (uint32_t)sizeof(S)));
+}
+
 template <int DIM, class SF, class T, class TG>
 __device__ __forceinline__ void pull(const LbmArgs<T> &a, int x, int y, int z, T *f, TG *g)
 {
@@ -281,32 +270,32 @@ __device__ __forceinline__ void pull(const LbmArgs<T> &a, int x, int y, int z, T
     nbr_axis(y, a.ny, a.per[1], nb.m[1], nb.p[1], nb.vm[1], nb.vp[1]);
     if (DIM == 3) nbr_axis(z, a.nz, a.per[2], nb.m[2], nb.p[2], nb.vm[2], nb.vp[2]);
     else { nb.m[2] = nb.p[2] = 0; nb.vm[2] = nb.vp[2] = true; }
-    const long long nx = a.nx, sxy = (long long)a.nx * a.ny;
-    // linear offsets of the upstream coordinate per axis: index by e + 1
-    const long long ox[3] = {(long long)nb.p[0], (long long)x, (long long)nb.m[0]};
-    const long long oy[3] = {nb.p[1] * nx, y * nx, nb.m[1] * nx};
-    const long long oz[3] = {nb.p[2] * sxy, z * sxy, nb.m[2] * sxy};
+    const uint32_t nx = (uint32_t)a.nx, sxy = (uint32_t)a.nx * (uint32_t)a.ny, Ns = (uint32_t)a.Ns;
+    // element offsets of the upstream coordinate per axis: index by e + 1
+    const uint32_t ox[3] = {(uint32_t)nb.p[0], (uint32_t)x, (uint32_t)nb.m[0]};
+    const uint32_t oy[3] = {(uint32_t)nb.p[1] * nx, (uint32_t)y * nx, (uint32_t)nb.m[1] * nx};
+    const uint32_t oz[3] = {(uint32_t)nb.p[2] * sxy, (uint32_t)z * sxy, (uint32_t)nb.m[2] * sxy};
     const bool vx[3] = {nb.vp[0], true, nb.vm[0]};
     const bool vy[3] = {nb.vp[1], true, nb.vm[1]};
     const bool vz[3] = {nb.vp[2], true, nb.vm[2]};
-    const long long self = oz[1] + oy[1] + ox[1];
+    const uint32_t self = oz[1] + oy[1] + ox[1];
     S fr[L::Q], gr[L::QG];
     bool gv[L::QG];
 #pragma unroll
     for (int q = 0; q < L::Q; ++q) {
         const int ex = L::e(q, 0) + 1, ey = L::e(q, 1) + 1, ez = L::e(q, 2) + 1;
+        const int o = L::opp(q), lo = q < o ? q : o;
         const bool v = vx[ex] && vy[ey] && vz[ez];
-        const S *src = v ? fa + (long long)q * a.Ns + (oz[ez] + oy[ey] + ox[ex])
-                         : fa + (long long)L::opp(q) * a.Ns + self;
-        fr[q] = *src;
+        const uint32_t off = v ? (uint32_t)(q - lo) * Ns + (oz[ez] + oy[ey] + ox[ex]) : (uint32_t)(o - lo) * Ns + self;
+        fr[q] = load_at(fa + (size_t)lo * a.Ns, off);
     }
 #pragma unroll
     for (int q = 0; q < L::QG; ++q) {
         const int ex = L::e(q, 0) + 1, ey = L::e(q, 1) + 1, ez = L::e(q, 2) + 1;
+        const int o = L::opp(q), lo = q < o ? q : o;
         gv[q] = vx[ex] && vy[ey] && vz[ez];
-        const S *src = gv[q] ? ga + (long long)q * a.Ns + (oz[ez] + oy[ey] + ox[ex])
-                             : ga + (long long)L::opp(q) * a.Ns + self;
-        gr[q] = *src;
+        const uint32_t off = gv[q] ? (uint32_t)(q - lo) * Ns + (oz[ez] + oy[ey] + ox[ex]) : (uint32_t)(o - lo) * Ns + self;
+        gr[q] = load_at(ga + (size_t)lo * a.Ns, off);
     }
     // every load of the node is issued before any value is used
     __builtin_amdgcn_sched_barrier(0);
@@ -452,7 +441,11 @@ __global__ __launch_bounds__(LBM_THREADS) void k_lbm(LbmArgs<typename SF::T> a)
     constexpr int RMAX = DIM == 3 ? 16 : 4;          // footprint rows per point
     constexpr int QCAP = 128 + 64 * RMAX;            // < 128 queued before each append
     constexpr int KSCAN = 4;                          // chunks whose loads are in flight together
-    __shared__ unsigned long long acc[NC][TL::N];     // fixed-point F_B, Q_B per tile node
+    // fixed-point F_B, Q_B per tile node; rows (fixed y, z) padded to X + 1
+    // words so that the rows of one point's footprint, queued on adjacent
+    // lanes, fall on different LDS banks
+    constexpr int PXU = TL::X + 1, NROW = TL::Y * TL::Z;
+    __shared__ unsigned long long acc[NC][NROW * PXU];
     __shared__ int queue[LBM_THREADS / 64][QCAP];
 
     // XCD-aware order: consecutive workgroups go to different XCDs (round
@@ -477,7 +470,7 @@ __global__ __launch_bounds__(LBM_THREADS) void k_lbm(LbmArgs<typename SF::T> a)
             pm0 = a.mk_start[p];
             pn = a.mk_start[p + 1] - pm0;
         }
-        for (int i = tid; i < NC * TL::N; i += LBM_THREADS) (&acc[0][0])[i] = 0ull;
+        for (int i = tid; i < NC * NROW * PXU; i += LBM_THREADS) (&acc[0][0])[i] = 0ull;
         __syncthreads();
         int *q = queue[wv];
         int qn = 0;                                   // wave-uniform queue length
@@ -502,7 +495,7 @@ __global__ __launch_bounds__(LBM_THREADS) void k_lbm(LbmArgs<typename SF::T> a)
         auto apply = [&](const Row &r) {
             const int ly = spread_axis(r.b.y - 1 + r.ky, a.ny, a.per[1]) - y0;
             const int lz = DIM == 3 ? spread_axis(r.b.z - 1 + r.kz, a.nz, a.per[2]) - z0 : 0;
-            const int row = TL::X * (ly + TL::Y * lz);
+            const int row = PXU * (ly + TL::Y * lz);
             const T wyz = r.wy * r.wz;
             T v[NC];
 #pragma unroll
@@ -620,7 +613,10 @@ __global__ __launch_bounds__(LBM_THREADS) void k_lbm(LbmArgs<typename SF::T> a)
         __syncthreads();
     }
 
-    const size_t sxy = (size_t)a.nx * a.ny;
+    const uint32_t nxu = (uint32_t)a.nx, sxy = (uint32_t)a.nx * (uint32_t)a.ny;
+    using C = typename SF::C;
+    using S = typename SF::S;
+    constexpr bool SR = sizeof(S) < 8;               // stochastic rounding of the stores
     bool bad = false;
 #pragma unroll 1
     for (int kk = 0; kk < TL::N / LBM_THREADS; ++kk) {
@@ -632,13 +628,12 @@ __global__ __launch_bounds__(LBM_THREADS) void k_lbm(LbmArgs<typename SF::T> a)
         // collision are formed in the compute type C (FP64 for FP32 storage:
         // in a slowly changing region FP32 arithmetic rounds the same way
         // every step and drifts by ~steps x ulp).
-        using C = typename SF::C;
         C FB[3] = {0, 0, 0};
         C QB = 0;
         if (has) {
 #pragma unroll
             for (int c = 0; c < NC; ++c) {
-                const C v = (C)((double)(long long)acc[c][ln] * SpreadFix<T>::INV);
+                const C v = (C)((double)(long long)acc[c][lr * PXU + lx] * SpreadFix<T>::INV);
                 if (c < DIM) FB[c] = v;
                 else QB = v;
             }
@@ -646,8 +641,26 @@ __global__ __launch_bounds__(LBM_THREADS) void k_lbm(LbmArgs<typename SF::T> a)
         T f[L::Q];
         C g[L::QG];
         pull<DIM, SF, T, C>(a, x, y, z, f, g);
-        C drho, j[3], dS;
-        moments<DIM, C>(f, g, drho, j, dS);
+        C fc[L::Q];
+#pragma unroll
+        for (int q = 0; q < L::Q; ++q) fc[q] = (C)f[q];
+        // raw moments rho - 1, j, S - T_ref, summed over opposite pairs
+        C drho = fc[0], j[3] = {0, 0, 0};
+#pragma unroll
+        for (int q = 1; q < L::Q; ++q) {
+            const int o = L::opp(q);
+            if (q > o) continue;
+            const C sp = fc[q] + fc[o], dm = fc[q] - fc[o];
+            drho += sp;
+#pragma unroll
+            for (int d = 0; d < DIM; ++d) {
+                if (L::e(q, d) > 0) j[d] += dm;
+                else if (L::e(q, d) < 0) j[d] -= dm;
+            }
+        }
+        C dS = 0;
+#pragma unroll
+        for (int q = 0; q < L::QG; ++q) dS += g[q];
         // Sec. 2.1 after Eq. (lbm3.5): T = S + Q_B / 2, u = (j + F / 2) / rho with
         // F = F_B + g beta (T - T_ref) e_up (buoyancy along +y in 2D, +z in 3D).
         const C rho = (C)1 + drho;
@@ -660,21 +673,33 @@ __global__ __launch_bounds__(LBM_THREADS) void k_lbm(LbmArgs<typename SF::T> a)
         for (int d = 0; d < DIM; ++d) u[d] = (j[d] + (C)0.5 * F[d]) * inv;
         const C uu = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
         bad = bad || !(uu <= (C)0.16) || !(rho > (C)0.5 && rho < (C)2);
-        const size_t n = (size_t)z * sxy + (size_t)y * a.nx + x;
+        const uint32_t n = (uint32_t)z * sxy + (uint32_t)y * nxu + (uint32_t)x;
         if (MACRO) {
-            a.macro[n] = (T)rho;
-            a.macro[a.Ns + n] = (T)u[0];
-            a.macro[2 * a.Ns + n] = (T)u[1];
-            a.macro[3 * a.Ns + n] = (T)u[2];
-            a.macro[4 * a.Ns + n] = (T)(a.Tref + (double)dT);
+            *addr_at(a.macro, n) = (T)rho;
+            *addr_at(a.macro + a.Ns, n) = (T)u[0];
+            *addr_at(a.macro + 2 * a.Ns, n) = (T)u[1];
+            *addr_at(a.macro + 3 * a.Ns, n) = (T)u[2];
+            *addr_at(a.macro + 4 * a.Ns, n) = (T)(a.Tref + (double)dT);
             continue;
         }
         const C uF = u[0] * F[0] + u[1] * F[1] + u[2] * F[2];
-        typename SF::S *fb = (typename SF::S *)a.fB;
-        typename SF::S *gb = (typename SF::S *)a.gB;
         const C omf = (C)a.omf, gf = (C)a.gf, omg = (C)a.omg, gg = (C)a.gg;
+        const uint32_t seed = SR ? node_seed(n, a.seed) : 0u;
+        S *fb = (S *)a.fB;
+        S *gb = (S *)a.gB;
+        // Forced BGK (Eqs. lbm2, lbm3, lbm9) as increments f* - f = src - omega (f - f^eq)
+        // over opposite pairs q, q' = -q.  With t = rho e.u, f^eq - w has the
+        // even part w (drho - 1.5 rho u.u + 4.5 t e.u) and the odd part 3 w t;
+        // the source has the even part w gf (9 e.u e.F - 3 u.F) and the odd
+        // part 3 w gf e.F.  So inc(q, q') = P +- M - omega f with
+        //   P = w (K3 + e.u (9 gf e.F + 4.5 omega t)),  M = 3 w (gf e.F + omega t),
+        //   K3 = omega (drho - 1.5 rho u.u) - 3 gf u.F.
+        const C K3 = omf * (drho - (C)1.5 * rho * uu) - (C)3 * gf * uF;
+        SF::st_sum(addr_at(fb, n), f[0], (C)L::w(0) * K3 - omf * fc[0], L::w(0), SR ? sr_bits(seed, 0) : 0u);
 #pragma unroll
-        for (int q = 0; q < L::Q; ++q) {
+        for (int q = 1; q < L::Q; ++q) {
+            const int o = L::opp(q);
+            if (q > o) continue;
             C eu = 0, eF = 0;
 #pragma unroll
             for (int d = 0; d < DIM; ++d) {
@@ -682,16 +707,26 @@ __global__ __launch_bounds__(LBM_THREADS) void k_lbm(LbmArgs<typename SF::T> a)
                 else if (L::e(q, d) < 0) { eu -= u[d]; eF -= F[d]; }
             }
             const C wq = (C)L::w(q);
-            // f^eq - w (Eq. lbm3) and the Guo source (Eq. lbm9)
-            const C feq = wq * (drho + rho * ((C)3 * eu + (C)4.5 * eu * eu - (C)1.5 * uu));
-            const C src = gf * wq * ((C)3 * (eF - uF) + (C)9 * eu * eF);
-            const C fq = (C)f[q];
-            SF::st_sum(fb + (size_t)q * a.Ns, n, f[q], src - omf * (fq - feq), L::w(q),
-                       unit_hash((uint32_t)n, (uint32_t)q, a.step));
+            const C t = rho * eu;
+            const C ge = gf * eF;
+            const C P = wq * (K3 + eu * ((C)9 * ge + (C)4.5 * omf * t));
+            const C M = (C)3 * wq * (ge + omf * t);
+            // both arrays of the pair from the pair's first one (q < o)
+            S *pb = fb + (size_t)q * a.Ns;
+            SF::st_sum(addr_at(pb, n), f[q], (P + M) - omf * fc[q], L::w(q), SR ? sr_bits(seed, q) : 0u);
+            SF::st_sum(addr_at(pb, (uint32_t)(o - q) * (uint32_t)a.Ns + n), f[o], (P - M) - omf * fc[o], L::w(o),
+                       SR ? sr_bits(seed, o) : 0u);
         }
+        // Thermal BGK with the linear equilibrium and the heat source
+        // (Eqs. lbm2.5, lbm12.5): inc = w (gg Q_B + omega_g dT) +- omega_g w T e.u / c_sg^2 - omega_g g.
         const C Tabs = (C)a.Tref + dT;
+        const C R = gg * QB + omg * dT;
+        const C Z = omg * Tabs * (C)L::csg2_inv;
+        SF::st_sum(addr_at(gb, n), (T)g[0], (C)L::wg(0) * R - omg * g[0], L::wg(0), SR ? sr_bits(seed, L::Q) : 0u);
 #pragma unroll
-        for (int q = 0; q < L::QG; ++q) {
+        for (int q = 1; q < L::QG; ++q) {
+            const int o = L::opp(q);
+            if (q > o) continue;
             C eu = 0;
 #pragma unroll
             for (int d = 0; d < DIM; ++d) {
@@ -699,10 +734,11 @@ __global__ __launch_bounds__(LBM_THREADS) void k_lbm(LbmArgs<typename SF::T> a)
                 else if (L::e(q, d) < 0) eu -= u[d];
             }
             const C wq = (C)L::wg(q);
-            // g^eq - w T_ref (linear thermal equilibrium) and the heat source (Eq. lbm12.5)
-            const C geq = wq * (dT + Tabs * eu * (C)L::csg2_inv);
-            SF::st_sum(gb + (size_t)q * a.Ns, n, g[q], gg * wq * QB - omg * (g[q] - geq), L::wg(q),
-                       unit_hash((uint32_t)n, (uint32_t)(32 + q), a.step));
+            const C P = wq * R, M = wq * Z * eu;
+            S *pb = gb + (size_t)q * a.Ns;
+            SF::st_sum(addr_at(pb, n), (T)g[q], (P + M) - omg * g[q], L::wg(q), SR ? sr_bits(seed, L::Q + q) : 0u);
+            SF::st_sum(addr_at(pb, (uint32_t)(o - q) * (uint32_t)a.Ns + n), (T)g[o], (P - M) - omg * g[o], L::wg(o),
+                       SR ? sr_bits(seed, L::Q + o) : 0u);
         }
     }
     if (bad) atomicOr(a.err, ERR_FIELD);
@@ -1356,10 +1392,10 @@ __global__ void k_init(void *f, void *g, int Q, long long N, long long Ns, typen
 {
     using S = typename SF::S;
     for (long long n = blockIdx.x * (long long)blockDim.x + threadIdx.x; n < N; n += (long long)gridDim.x * blockDim.x) {
-        for (int q = 0; q < Q; ++q) SF::st((S *)f + (size_t)q * Ns, n, (typename SF::T)0, 1.0);
+        for (int q = 0; q < Q; ++q) SF::st((S *)f + (size_t)q * Ns + n, (typename SF::T)0, 1.0);
         for (int q = 0; q < QG; ++q) {
             const double w = q == 0 ? wg0 : wg1;
-            SF::st((S *)g + (size_t)q * Ns, n, (typename SF::T)(w * (double)dTinit), w);
+            SF::st((S *)g + (size_t)q * Ns + n, (typename SF::T)(w * (double)dTinit), w);
         }
     }
 }
