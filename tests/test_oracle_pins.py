@@ -304,6 +304,47 @@ def test_spread_force_sums_to_marker_forces(oracle_mod):
     assert QB.sum() == pytest.approx(r[6], rel=1e-12)
 
 
+def test_stokes_drag_periodic_array(oracle_mod):
+    """P9: a fixed sphere (R = 3) in a periodic 32^3 box, the fluid driven by a
+    uniform force (the buoyancy term with T - T_ref = 1 and no heat
+    exchange).  At Re << 1 the drag and the mean fluid velocity U obey
+    Stokes' law with Hasimoto's factor K(phi) for a simple cubic array,
+    F = 6 pi mu a U K.  For a diffuse interface spread by the 4-point kernel
+    the hydrodynamic radius a exceeds the point radius by a fraction of a
+    lattice unit: R <= a <= R + 1.  The fluid starts at the expected mean
+    velocity so the quasi-steady ratio settles within a few hundred steps;
+    it must also be steady (two readings 200 steps apart agree)."""
+    L, R, tau, gb = 32, 3.0, 1.0, 1e-6
+    nu = (tau - 0.5) / 3.0
+    cfg = base3d(nx=L, ny=L, nz=L, nu=nu, T_init=1.0, T_ref=0.0, gbeta=gb)
+    c = (L - 1) / 2.0
+    o = oracle_mod.Oracle(cfg, np.array([prow((c, c, c), R, T=1.0, flags=W.FIXED)]))
+    phi = 4.0 / 3.0 * math.pi * R ** 3 / L ** 3
+    K = 1.0 / (1.0 - 1.7601 * phi ** (1.0 / 3.0) + phi - 1.5593 * phi ** 2)
+    F = gb * L ** 3                                  # total driving force = drag at steady state
+    u0 = F / (6.0 * math.pi * nu * (R + 0.5) * K)
+    # equilibrium at u = (0, 0, u0) in the D3Q19 order of the populations
+    f, g = o.populations()
+    ez = np.array([0, 0, 0, 0, 0, 1, -1, 0, 0, 0, 0, 1, -1, -1, 1, 1, -1, -1, 1], dtype=float)
+    w = np.array([1 / 3] + [1 / 18] * 6 + [1 / 36] * 12)
+    f[:] = (w * (1.0 + 3.0 * ez * u0 + 4.5 * (ez * u0) ** 2 - 1.5 * u0 ** 2))[:, None]
+    o.set_populations(f, g)
+    assert o.totals()[3] / L ** 3 == pytest.approx(u0, rel=1e-9)      # the order assumed above
+
+    def radius():
+        U = o.totals()[3] / L ** 3
+        drag = o.reactions()[0][2]
+        assert 0 < U * 2 * R / nu < 0.1            # Stokes regime
+        return drag / (6.0 * math.pi * nu * K * U)
+
+    o.step(600)
+    a1 = radius()
+    o.step(200)
+    a2 = radius()
+    assert abs(a2 - a1) < 1e-2 * a2
+    assert R <= a2 <= R + 1.0
+
+
 def test_fixed_hot_body_heats_fluid_and_drag_opposes_motion(oracle_mod):
     """Sign checks of Eqs. (lbm7)-(lbm8), (lbm13): a body pushed through fluid
     at rest feels a force against its velocity; a hot body heats the fluid."""
