@@ -185,6 +185,56 @@ int pibm_profile_read(pibm_ctx *ctx, double *ms, long long *count);
 /* Release the context (not the caller's workspace or stream). */
 int pibm_destroy(pibm_ctx *ctx);
 
+/* ------------------------------------------------------------------------
+ * Learned per-particle closure (not in the paper; it replaces the resolved
+ * PIBM exchange of Sec. 2.2 in the coarse, one-point-per-particle mode):
+ * a multilayer perceptron 16 -> 128 -> 128 -> 128 -> 4 with GELU (erf form)
+ * hidden units.  Inputs are 16 normalised features per particle, outputs 4
+ * normalised targets (drag, two lift components, Nusselt number); the
+ * normalisation is the caller's.  Arithmetic: BF16 operands on the matrix
+ * cores with FP32 accumulation, FP32 master weights and Adam state.
+ *
+ * Parameters, canonical order (FP32): W1[16][128], b1[128], W2[128][128],
+ * b2[128], W3[128][128], b3[128], W4[128][4], b4[4]; layer l computes
+ * z = h W_l + b_l.  The loss of a batch of n samples is
+ * L = sum_s sum_c (y_sc - t_sc)^2 / (4 n).
+ * ------------------------------------------------------------------------ */
+enum { PIBM_MLP_IN = 16, PIBM_MLP_HIDDEN = 128, PIBM_MLP_OUT = 4, PIBM_MLP_NPARAM = 35716 };
+typedef struct pibm_mlp pibm_mlp;
+
+/* Device workspace for a network trained on batches of up to max_batch
+ * samples (master weights, Adam moments, BF16 copies, per-workgroup gradient
+ * slots).  Returns 0 if max_batch < 1. */
+size_t pibm_mlp_workspace_bytes(int max_batch);
+
+/* Create a network with weights U(-1/sqrt(fan_in), 1/sqrt(fan_in)) drawn by
+ * splitmix64 from `seed` and zero biases.  dev_workspace: 256-byte aligned,
+ * >= pibm_mlp_workspace_bytes(max_batch), owned by the caller; hip_stream: the
+ * caller's stream (NULL = default). */
+int pibm_mlp_create(pibm_mlp **out, unsigned long long seed, int max_batch, void *dev_workspace,
+                    size_t workspace_bytes, void *hip_stream);
+
+/* Host copies of the FP32 parameters (PIBM_MLP_NPARAM floats, canonical
+ * order).  set_params rejects non-finite values and restarts Adam. */
+int pibm_mlp_set_params(pibm_mlp *m, const float *host_params);
+int pibm_mlp_get_params(pibm_mlp *m, float *host_params);
+
+/* Inference: dev_y[n][4] (FP32, 16-byte aligned) from dev_x[n][16] (BF16 bit
+ * patterns, 8-byte aligned), both device pointers.  Asynchronous. */
+int pibm_mlp_forward(pibm_mlp *m, const void *dev_x, float *dev_y, int n);
+
+/* Gradient dL/dparam of one batch (1 <= n <= max_batch), copied to
+ * host_grads[PIBM_MLP_NPARAM]; the loss to *loss if not NULL.  dev_t[n][4]
+ * FP32 targets.  Parameters are not changed.  Synchronises. */
+int pibm_mlp_grads(pibm_mlp *m, const void *dev_x, const float *dev_t, int n, float *host_grads, double *loss);
+
+/* One Adam step (beta1 0.9, beta2 0.999, eps 1e-8, bias-corrected) with
+ * learning rate lr on one batch; the batch loss before the step to *loss if
+ * not NULL (then synchronises). */
+int pibm_mlp_train_step(pibm_mlp *m, const void *dev_x, const float *dev_t, int n, float lr, double *loss);
+
+int pibm_mlp_destroy(pibm_mlp *m);
+
 /* Static description of a status code. */
 const char *pibm_strerror(int status);
 

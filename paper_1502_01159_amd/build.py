@@ -6,7 +6,7 @@ import subprocess
 import sys
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-SOURCES = [os.path.join(_HERE, "csrc", "pibm.hip")]
+SOURCES = [os.path.join(_HERE, "csrc", "pibm.hip"), os.path.join(_HERE, "csrc", "pibm_mlp.hip")]
 OUT = os.path.join(_HERE, "libpibm.so")
 
 HIPCC_FLAGS = [

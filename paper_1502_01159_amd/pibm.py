@@ -25,7 +25,10 @@ EXPORTS = [
     "pibm_fields", "pibm_get_populations", "pibm_set_populations", "pibm_num_nodes", "pibm_num_markers",
     "pibm_step_count", "pibm_derived", "pibm_save", "pibm_load", "pibm_destroy", "pibm_strerror",
     "pibm_profile", "pibm_profile_read",
+    "pibm_mlp_workspace_bytes", "pibm_mlp_create", "pibm_mlp_set_params", "pibm_mlp_get_params",
+    "pibm_mlp_forward", "pibm_mlp_grads", "pibm_mlp_train_step", "pibm_mlp_destroy",
 ]
+MLP_IN, MLP_HIDDEN, MLP_OUT, MLP_NPARAM = 16, 128, 4, 35716
 PHASES = ("markers", "bin", "lattice", "dem")
 
 
@@ -91,6 +94,16 @@ def lib():
         L.pibm_profile_read.argtypes = [vp, dp, ctypes.POINTER(ctypes.c_longlong)]
         L.pibm_strerror.restype = ctypes.c_char_p
         L.pibm_strerror.argtypes = [ctypes.c_int]
+        fp = ctypes.POINTER(ctypes.c_float)
+        L.pibm_mlp_workspace_bytes.restype = sz
+        L.pibm_mlp_workspace_bytes.argtypes = [ctypes.c_int]
+        L.pibm_mlp_create.argtypes = [ctypes.POINTER(vp), ctypes.c_ulonglong, ctypes.c_int, vp, sz, vp]
+        L.pibm_mlp_set_params.argtypes = [vp, fp]
+        L.pibm_mlp_get_params.argtypes = [vp, fp]
+        L.pibm_mlp_forward.argtypes = [vp, vp, vp, ctypes.c_int]
+        L.pibm_mlp_grads.argtypes = [vp, vp, vp, ctypes.c_int, fp, dp]
+        L.pibm_mlp_train_step.argtypes = [vp, vp, vp, ctypes.c_int, ctypes.c_float, dp]
+        L.pibm_mlp_destroy.argtypes = [vp]
         _lib = L
     return _lib
 
@@ -285,3 +298,95 @@ class Simulation:
     def load(self, blob: bytes):
         buf = ctypes.create_string_buffer(blob, len(blob))
         self._check(lib().pibm_load(self._h, buf, len(blob)), "pibm_load")
+
+
+class Mlp:
+    """The closure network (``pibm_mlp_*``) on the current CUDA device.
+
+    Inputs are torch tensors on the device: ``x`` of shape (n, 16) and dtype
+    bfloat16, targets ``t`` of shape (n, 4) float32.  Parameters are numpy
+    float32 vectors in the canonical order of ``include/pibm.h``."""
+
+    def __init__(self, seed: int = 0, max_batch: int = 4096):
+        import torch
+
+        L = lib()
+        self._torch = torch
+        nbytes = L.pibm_mlp_workspace_bytes(int(max_batch))
+        if nbytes == 0:
+            raise PibmError(EINVAL, "pibm_mlp_workspace_bytes")
+        self._ws = torch.empty(nbytes + 256, dtype=torch.uint8, device="cuda")
+        base = self._ws.data_ptr()
+        aligned = (base + 255) // 256 * 256
+        self._stream = torch.cuda.current_stream().cuda_stream
+        h = ctypes.c_void_p()
+        st = L.pibm_mlp_create(ctypes.byref(h), int(seed), int(max_batch), ctypes.c_void_p(aligned),
+                               nbytes, ctypes.c_void_p(self._stream))
+        if st != OK:
+            raise PibmError(st, "pibm_mlp_create")
+        self._h = h
+        self.max_batch = int(max_batch)
+
+    @staticmethod
+    def _check(x, t=None):
+        import torch
+
+        if x.dtype != torch.bfloat16 or x.dim() != 2 or x.shape[1] != MLP_IN or not x.is_contiguous() or not x.is_cuda:
+            raise ValueError("x must be a contiguous CUDA bfloat16 tensor of shape (n, 16)")
+        if t is not None and (t.dtype != torch.float32 or tuple(t.shape) != (x.shape[0], MLP_OUT)
+                              or not t.is_contiguous() or not t.is_cuda):
+            raise ValueError("t must be a contiguous CUDA float32 tensor of shape (n, 4)")
+
+    def get_params(self) -> np.ndarray:
+        out = np.empty(MLP_NPARAM, dtype=np.float32)
+        st = lib().pibm_mlp_get_params(self._h, out.ctypes.data_as(ctypes.POINTER(ctypes.c_float)))
+        if st != OK:
+            raise PibmError(st, "pibm_mlp_get_params")
+        return out
+
+    def set_params(self, p):
+        p = np.ascontiguousarray(p, dtype=np.float32)
+        if p.size != MLP_NPARAM:
+            raise ValueError("wrong parameter count")
+        st = lib().pibm_mlp_set_params(self._h, p.ctypes.data_as(ctypes.POINTER(ctypes.c_float)))
+        if st != OK:
+            raise PibmError(st, "pibm_mlp_set_params")
+
+    def forward(self, x, y=None):
+        self._check(x)
+        if y is None:
+            y = self._torch.empty((x.shape[0], MLP_OUT), dtype=self._torch.float32, device=x.device)
+        st = lib().pibm_mlp_forward(self._h, ctypes.c_void_p(x.data_ptr()), ctypes.c_void_p(y.data_ptr()), x.shape[0])
+        if st != OK:
+            raise PibmError(st, "pibm_mlp_forward")
+        return y
+
+    def grads(self, x, t):
+        self._check(x, t)
+        g = np.empty(MLP_NPARAM, dtype=np.float32)
+        loss = ctypes.c_double()
+        st = lib().pibm_mlp_grads(self._h, ctypes.c_void_p(x.data_ptr()), ctypes.c_void_p(t.data_ptr()), x.shape[0],
+                                  g.ctypes.data_as(ctypes.POINTER(ctypes.c_float)), ctypes.byref(loss))
+        if st != OK:
+            raise PibmError(st, "pibm_mlp_grads")
+        return loss.value, g
+
+    def train_step(self, x, t, lr: float) -> float:
+        self._check(x, t)
+        loss = ctypes.c_double()
+        st = lib().pibm_mlp_train_step(self._h, ctypes.c_void_p(x.data_ptr()), ctypes.c_void_p(t.data_ptr()),
+                                       x.shape[0], float(lr), ctypes.byref(loss))
+        if st != OK:
+            raise PibmError(st, "pibm_mlp_train_step")
+        return loss.value
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().pibm_mlp_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -1,0 +1,163 @@
+"""The closure network's GPU kernels (BF16 matrix cores, FP32 accumulation)
+against the FP64 oracle that mirrors their BF16 rounding points, through the
+C ABI."""
+import math
+
+import numpy as np
+import pytest
+
+from oracle import mlp_oracle as M
+from paper_1502_01159_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def torch_mod():
+    torch = pytest.importorskip("torch")
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch
+
+
+@pytest.fixture(scope="module")
+def pibm_mod(torch_mod):
+    from paper_1502_01159_amd import pibm
+    return pibm
+
+
+def params(seed):
+    rng = W.SplitMix64(seed)
+    p = np.empty(M.NPARAM)
+    k = 0
+    for i, o in M.SIZES:
+        lim = 1.7 / math.sqrt(i)
+        p[k:k + i * o] = (2.0 * rng.uniforms(i * o) - 1.0) * lim
+        k += i * o
+        p[k:k + o] = (2.0 * rng.uniforms(o) - 1.0) * 0.2
+        k += o
+    return p.astype(np.float32)
+
+
+def batch(seed, n):
+    rng = np.random.default_rng(seed)
+    x = M.bf16(rng.uniform(-2, 2, size=(n, 16)))
+    t = rng.uniform(-1, 1, size=(n, 4)).astype(np.float32)
+    return x, t
+
+
+def to_dev(torch, x, t=None):
+    xd = torch.tensor(x, dtype=torch.float32).to(torch.bfloat16).cuda().contiguous()
+    td = None if t is None else torch.tensor(t, dtype=torch.float32).cuda().contiguous()
+    return xd, td
+
+
+BLOCKS = ["W1", "b1", "W2", "b2", "W3", "b3", "W4", "b4"]
+
+
+def blocks(v):
+    out, k = {}, 0
+    for l, (i, o) in enumerate(M.SIZES):
+        out[f"W{l + 1}"] = v[k:k + i * o]
+        k += i * o
+        out[f"b{l + 1}"] = v[k:k + o]
+        k += o
+    return out
+
+
+@pytest.mark.parametrize("n", [1, 37, 1000])
+def test_forward_matches_mirrored_oracle(torch_mod, pibm_mod, n):
+    torch = torch_mod
+    m = pibm_mod.Mlp(seed=1, max_batch=1024)
+    p = params(5)
+    m.set_params(p)
+    x, _ = batch(6, n)
+    xd, _ = to_dev(torch, x)
+    y = m.forward(xd).cpu().numpy().astype(np.float64)
+    ym = M.forward(p.astype(np.float64), x, mirror=True)
+    ye = M.forward(p.astype(np.float64), x, mirror=False)
+    scale = np.abs(ym).max()
+    # FP32 accumulation order and the FP32 GELU only move BF16 rounding
+    # decisions: a few in 10^3 relative
+    assert np.linalg.norm(y - ym) <= 1e-3 * np.linalg.norm(ym)
+    assert np.abs(y - ym).max() <= 1e-2 * scale
+    # and the mirror is the right model: the exact FP64 network is further away
+    assert np.linalg.norm(y - ye) > np.linalg.norm(y - ym)
+    m.close()
+
+
+def test_gradients_match_mirrored_oracle(torch_mod, pibm_mod):
+    torch = torch_mod
+    n = 300                                      # 5 workgroups, the last one ragged
+    m = pibm_mod.Mlp(seed=1, max_batch=512)
+    p = params(7)
+    m.set_params(p)
+    x, t = batch(8, n)
+    xd, td = to_dev(torch, x, t)
+    loss, g = m.grads(xd, td)
+    lm, gm = M.loss_and_grads(p.astype(np.float64), x, t.astype(np.float64), mirror=True)
+    assert loss == pytest.approx(lm, rel=1e-3)
+    G, Gm = blocks(g.astype(np.float64)), blocks(gm)
+    for k in BLOCKS:
+        err = np.linalg.norm(G[k] - Gm[k]) / np.linalg.norm(Gm[k])
+        assert err <= 1e-3 * 3, (k, err)
+    # parameters untouched
+    assert np.array_equal(m.get_params(), p)
+    m.close()
+
+
+def test_adam_first_step_and_reproducibility(torch_mod, pibm_mod):
+    torch = torch_mod
+    n, lr = 256, 1e-3
+    x, t = batch(9, n)
+    xd, td = to_dev(torch, x, t)
+    p = params(10)
+    m = pibm_mod.Mlp(seed=2, max_batch=n)
+    m.set_params(p)
+    _, g = m.grads(xd, td)
+    m.train_step(xd, td, lr)
+    p1 = m.get_params().astype(np.float64)
+    # Adam's first bias-corrected step is lr * g / (|g| + eps)
+    expect = p.astype(np.float64) - lr * g / (np.abs(g) + 1e-8)
+    assert np.allclose(p1, expect, rtol=0, atol=2e-7 + 1e-6 * np.abs(p).max())
+    # a second network from the same state gives the same bits
+    m2 = pibm_mod.Mlp(seed=3, max_batch=n)
+    m2.set_params(p)
+    m2.train_step(xd, td, lr)
+    assert np.array_equal(m2.get_params(), m.get_params())
+    m.close()
+    m2.close()
+
+
+def test_training_reduces_loss(torch_mod, pibm_mod):
+    """A smooth target of the inputs is learnable: 300 Adam steps on batches
+    of 1024 cut the loss at least tenfold."""
+    torch = torch_mod
+    rng = np.random.default_rng(11)
+    n = 1024
+    A = rng.normal(size=(16, 4)) / 4.0
+    m = pibm_mod.Mlp(seed=4, max_batch=n)
+    first = last = None
+    for it in range(300):
+        x = M.bf16(rng.uniform(-1, 1, size=(n, 16)))
+        t = np.tanh(x @ A).astype(np.float32)
+        xd, td = to_dev(torch, x, t)
+        L = m.train_step(xd, td, 2e-3)
+        first = L if first is None else first
+        last = L
+    assert last < 0.1 * first, (first, last)
+    m.close()
+
+
+def test_rejects_bad_arguments(torch_mod, pibm_mod):
+    torch = torch_mod
+    m = pibm_mod.Mlp(seed=1, max_batch=64)
+    x, t = batch(12, 65)
+    xd, td = to_dev(torch, x, t)
+    with pytest.raises(pibm_mod.PibmError):
+        m.grads(xd, td)                          # beyond max_batch
+    with pytest.raises(pibm_mod.PibmError):
+        m.set_params(np.full(M.NPARAM, np.nan, dtype=np.float32))
+    y = m.forward(xd[:0])                        # empty batch is a no-op
+    assert y.shape == (0, 4)
+    m.close()
