@@ -81,6 +81,8 @@ def lib():
         L.orc_get_markers.argtypes = [vp, ctypes.c_int, dp]
         L.orc_fields.argtypes = [vp, dp, dp, dp, dp, dp]
         L.orc_totals.argtypes = [vp, dp]
+        L.orc_raw_moments.argtypes = [vp, dp, dp, dp]
+        L.orc_exchange.argtypes = [vp]
         L.orc_contacts.argtypes = [vp, ctypes.c_int, ip]
         L.orc_delta_h.restype = ctypes.c_double
         L.orc_delta_h.argtypes = [ctypes.c_double]
@@ -231,6 +233,17 @@ class Oracle:
         if forcing:
             out = out + (FB.reshape(self.shape + (3,)), QB.reshape(self.shape))
         return out
+
+    def raw_moments(self):
+        """Post-stream rho (N), j (N, 3), S (N) of the current state."""
+        rho, j, S = np.empty(self.N), np.empty(3 * self.N), np.empty(self.N)
+        lib().orc_raw_moments(self._h, _dp(rho), _dp(j), _dp(S))
+        return rho, j.reshape(self.N, 3), S
+
+    def exchange(self):
+        """Evaluate the point exchange on the current state; its reactions
+        become what reactions() returns."""
+        lib().orc_exchange(self._h)
 
     def totals(self):
         out = np.empty(5)

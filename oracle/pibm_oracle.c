@@ -803,6 +803,28 @@ void orc_fields(orc_state *s, double *rho, double *u, double *T, double *FB, dou
     }
 }
 
+/* Raw post-stream moments of the current state (the exchange's inputs,
+ * Sec. 2.2): rho[N], j[3N], S[N] with S = sum g; the state is not advanced. */
+void orc_raw_moments(orc_state *s, double *rho, double *j, double *S)
+{
+    stream(s);
+    moments(s);
+    for (long n = 0; n < s->N; n++) {
+        rho[n] = s->rho[n];
+        j[3*n] = s->j[3*n]; j[3*n+1] = s->j[3*n+1]; j[3*n+2] = s->j[3*n+2];
+        S[n] = s->S[n];
+    }
+}
+
+/* The Lagrangian-point exchange and reactions (Eqs. lbm5-lbm8, lbm13) of the
+ * current state, recorded as the reactions; the state is not advanced. */
+void orc_exchange(orc_state *s)
+{
+    stream(s);
+    moments(s);
+    pibm(s, 1);
+}
+
 /* Lagrange weight of one corner (for pins): product over axes of the i_max=2
  * polynomial of Eq. (lbm6). */
 double orc_lagrange2(double X, int node, int other)

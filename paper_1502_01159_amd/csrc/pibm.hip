@@ -10,6 +10,7 @@
 // buffer is carved from the caller's workspace.
 #include "pibm_device.h"
 #include "../../include/pibm.h"
+#include "pibm_internal.h"
 
 #include <algorithm>
 #include <cmath>
@@ -28,7 +29,7 @@ size_t up(size_t v) { return (v + ALIGN - 1) / ALIGN * ALIGN; }
 enum Region {
     R_FA, R_GA, R_FB, R_GB, R_PART0, R_PART1, R_REACT, R_TMPL, R_TMPL_START, R_TMPL_REXT, R_MK_START, R_MK,
     R_TCOUNT, R_TSTART, R_TFILL, R_TITEMS, R_CCOUNT, R_CSTART, R_CFILL, R_CITEMS, R_NBR, R_NBRN, R_XREF,
-    R_HID0, R_HXI0, R_HN0, R_HID1, R_HXI1, R_HN1, R_ERR, R_COUNT
+    R_HID0, R_HXI0, R_HN0, R_HID1, R_HXI1, R_HN1, R_FEAT, R_TARG, R_AUX, R_XBF, R_YMLP, R_NORM, R_ERR, R_COUNT
 };
 
 struct Template {
@@ -233,6 +234,12 @@ int make_plan(const pibm_params *p, const pibm_particle *pt, int np, Plan &P)
     sz[R_HID0] = sz[R_HID1] = npa * MAXC * sizeof(int);
     sz[R_HXI0] = sz[R_HXI1] = npa * MAXC * 3 * sizeof(double);
     sz[R_HN0] = sz[R_HN1] = npa * sizeof(int);
+    sz[R_FEAT] = npa * 16 * sizeof(float);
+    sz[R_TARG] = npa * 4 * sizeof(float);
+    sz[R_AUX] = npa * 4 * sizeof(float);
+    sz[R_XBF] = npa * 16 * sizeof(uint16_t);
+    sz[R_YMLP] = npa * 4 * sizeof(float);
+    sz[R_NORM] = 64 * sizeof(float);
     sz[R_ERR] = 64;
     size_t o = 0;
     for (int r = 0; r < R_COUNT; ++r) { P.off[r] = o; o += up(sz[r]); }
@@ -320,6 +327,7 @@ struct pibm_ctx {
     long long step;
     int sticky;
     int device_lost;
+    pibm_mlp *closure = nullptr;   // learned closure in the one-point mode (not owned)
     // phase profiling: pairs of events recorded around each phase's launches
     int prof_on = 0;
     std::vector<hipEvent_t> ev_free;
@@ -383,6 +391,44 @@ int launch_markers(pibm_ctx *c, bool reactions)
     m.kappa = c->p.kappa_T;
     m.Tref = c->p.T_ref;
     hipLaunchKernelGGL((k_markers<DIM, SF>), dim3(c->P.np), dim3(256), 0, c->stream, m);
+    return hip_ok(c, hipGetLastError());
+}
+
+template <int DIM, class SF>
+int launch_features(pibm_ctx *c, int filter, bool raw, bool for_network)
+{
+    using T = typename SF::T;
+    if (c->P.np == 0) return PIBM_OK;
+    FeatArgs<T> f{};
+    f.lb = lbm_args<T>(c);
+    f.part = (const DevParticle *)c->r(c->pcur ? R_PART1 : R_PART0);
+    f.np = c->P.np;
+    f.filter = filter;
+    f.nu = c->d.nu;
+    f.alpha = c->d.alpha;
+    f.gbeta = c->d.gbeta;
+    f.feat = raw ? (float *)c->r(R_FEAT) : nullptr;
+    f.aux = (float *)c->r(R_AUX);
+    f.xbf = for_network ? (uint16_t *)c->r(R_XBF) : nullptr;
+    f.norm = (const float *)c->r(R_NORM);
+    hipLaunchKernelGGL((k_features<DIM, SF>), dim3(c->P.np), dim3(FEAT_THREADS), 0, c->stream, f);
+    return hip_ok(c, hipGetLastError());
+}
+
+// The learned closure in place of the Lagrangian-point exchange: features of
+// the current state, the network, and its outputs as point forces and heat.
+template <int DIM, class SF>
+int launch_closure(pibm_ctx *c)
+{
+    using T = typename SF::T;
+    if (c->P.np == 0) return PIBM_OK;
+    int st;
+    if ((st = launch_features<DIM, SF>(c, 1, false, true))) return st;
+    if ((st = pibm_mlp_forward_on(c->closure, c->r(R_XBF), (float *)c->r(R_YMLP), c->P.np, c->stream))) return st;
+    hipLaunchKernelGGL((k_closure<DIM, T>), dim3((c->P.np + 127) / 128), dim3(128), 0, c->stream,
+                       (const DevParticle *)c->r(c->pcur ? R_PART1 : R_PART0), c->P.np, (const float *)c->r(R_YMLP),
+                       (const float *)c->r(R_NORM), (const float *)c->r(R_AUX), c->d.nu, c->d.alpha,
+                       (MarkerRec<T> *)c->r(R_MK), (DevReact *)c->r(R_REACT), (const int *)c->r(R_ERR));
     return hip_ok(c, hipGetLastError());
 }
 
@@ -525,7 +571,10 @@ int step_impl(pibm_ctx *c, int n)
 {
     for (int s = 0; s < n; ++s) {
         int st;
-        { PhaseTimer t(c, PIBM_PHASE_MARKERS); if ((st = launch_markers<DIM, SF>(c, true))) return st; }
+        {
+            PhaseTimer t(c, PIBM_PHASE_MARKERS);
+            if ((st = c->closure ? launch_closure<DIM, SF>(c) : launch_markers<DIM, SF>(c, true))) return st;
+        }
         { PhaseTimer t(c, PIBM_PHASE_BIN); if ((st = launch_bin(c))) return st; }
         { PhaseTimer t(c, PIBM_PHASE_LATTICE); if ((st = launch_lbm<DIM, SF, false>(c))) return st; }
         { PhaseTimer t(c, PIBM_PHASE_DEM); if ((st = launch_dem(c))) return st; }
@@ -539,7 +588,7 @@ template <int DIM, class SF>
 int macro_impl(pibm_ctx *c)
 {
     int st;
-    if ((st = launch_markers<DIM, SF>(c, false))) return st;
+    if ((st = c->closure ? launch_closure<DIM, SF>(c) : launch_markers<DIM, SF>(c, false))) return st;
     if ((st = launch_bin(c))) return st;
     return launch_lbm<DIM, SF, true>(c);
 }
@@ -557,6 +606,21 @@ int dispatch(pibm_ctx *c, A... args)
 }
 
 template <int DIM, class SF> struct StepOp { static int run(pibm_ctx *c, int n) { return step_impl<DIM, SF>(c, n); } };
+
+// Features of the current state, the resolved exchange's reactions for it,
+// and the targets in the same slip frame.
+template <int DIM, class SF>
+int features_impl(pibm_ctx *c, int filter)
+{
+    int st;
+    if ((st = launch_features<DIM, SF>(c, filter, true, false))) return st;
+    if ((st = launch_markers<DIM, SF>(c, true))) return st;
+    hipLaunchKernelGGL((k_targets<DIM>), dim3((c->P.np + 127) / 128), dim3(128), 0, c->stream,
+                       (const DevParticle *)c->r(c->pcur ? R_PART1 : R_PART0), c->P.np, (const DevReact *)c->r(R_REACT),
+                       (const float *)c->r(R_AUX), c->d.nu, c->d.alpha, (float *)c->r(R_TARG));
+    return hip_ok(c, hipGetLastError());
+}
+template <int DIM, class SF> struct FeatOp { static int run(pibm_ctx *c, int filter) { return features_impl<DIM, SF>(c, filter); } };
 template <int DIM, class SF> struct MacroOp { static int run(pibm_ctx *c) { return macro_impl<DIM, SF>(c); } };
 template <int DIM, class SF> struct InitOp {
     static int run(pibm_ctx *c) {
@@ -778,6 +842,41 @@ int pibm_fields(pibm_ctx *c, double *rho, double *u, double *T)
         if (T) T[n] = get(4, n);
     }
     return st;
+}
+
+int pibm_features(pibm_ctx *c, int filter, float *x, float *t)
+{
+    if (!c || filter < 1 || filter > 16) return PIBM_EINVAL;
+    if (c->device_lost) return PIBM_EDEVICE;
+    if (c->sticky) return c->sticky;
+    if (c->P.np == 0) return PIBM_OK;
+    int st = dispatch<FeatOp>(c, filter);
+    if (st) return st;
+    const size_t np = (size_t)c->P.np;
+    hipError_t e = hipSuccess;
+    if (x) e = hipMemcpyAsync(x, c->r(R_FEAT), np * 16 * sizeof(float), hipMemcpyDeviceToHost, c->stream);
+    if (e == hipSuccess && t) e = hipMemcpyAsync(t, c->r(R_TARG), np * 4 * sizeof(float), hipMemcpyDeviceToHost, c->stream);
+    if (e != hipSuccess) return hip_ok(c, e);
+    return sync_impl(c);
+}
+
+int pibm_set_closure(pibm_ctx *c, pibm_mlp *m, const float *norm)
+{
+    if (!c) return PIBM_EINVAL;
+    if (c->device_lost) return PIBM_EDEVICE;
+    if (!m) { c->closure = nullptr; return PIBM_OK; }
+    if (c->p.marker_mode != PIBM_MARKERS_POINT || !norm) return PIBM_EINVAL;
+    for (int i = 0; i < 40; ++i)
+        if (!std::isfinite(norm[i])) return PIBM_EINVAL;
+    for (int i = 0; i < 16; ++i)
+        if (!(norm[16 + i] > 0.f)) return PIBM_EINVAL;
+    for (int i = 0; i < 4; ++i)
+        if (!(norm[36 + i] > 0.f)) return PIBM_EINVAL;
+    hipError_t e = hipMemcpyAsync(c->r(R_NORM), norm, 40 * sizeof(float), hipMemcpyHostToDevice, c->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    if (e != hipSuccess) return hip_ok(c, e);
+    c->closure = m;
+    return PIBM_OK;
 }
 
 int pibm_get_populations(pibm_ctx *c, double *f, double *g)

@@ -987,6 +987,300 @@ __global__ __launch_bounds__(256) void k_markers(MkArgs<typename SF::T> a)
     }
 }
 
+
+// --------------------------------------------------------------------------
+// Closure features and targets per particle (the learned closure's inputs and
+// outputs; not in the paper).  All dimensionless, so that they carry over
+// from a resolved lattice to one coarsened by diffusive scaling:
+//   fluid seen by the particle: the raw moments (rho, j, S, no forcing terms)
+//     averaged over blocks of b^d nodes, linearly interpolated between the
+//     2^d block centres around the particle centre (b = 4 on a resolved
+//     lattice, b = 1 on a coarse one);
+//   slip s = U_f - U_p and its frame e1 = s/|s|, e2 = the up axis made
+//     normal to e1 (x if s is nearly vertical), e3 = e1 x e2 (2D: e2 = e1
+//     turned by +90 degrees);
+//   x = [Re_p = |s| D / nu, Gr_p = g beta (T_p - T_f) D^3 / nu^2, phi,
+//        T_p - T_f, offsets of the 4 (2D: 6) nearest centres in the frame / D
+//        (missing neighbours at 4, 4, 4)], phi = solid volume (area) of the
+//        particles whose centres lie within 2 D, over that ball (disk);
+//   t = [F.e1, F.e2, F.e3 (2D: 0)] / (rho0 nu^2) and H / (pi D alpha) in 3D,
+//       H / (pi alpha) per unit depth in 2D, from the last step's reactions.
+// One workgroup (256 threads) per particle; block sums reduced in a fixed
+// order; neighbours by a full scan with ties broken by index.
+// --------------------------------------------------------------------------
+constexpr int FEAT_THREADS = 256;
+constexpr int FEAT_NB = 4;                      // neighbours kept (3D); 2D keeps 6
+
+template <typename T> struct FeatArgs {
+    LbmArgs<T> lb;
+    const DevParticle *part;
+    int np, filter;
+    double nu, alpha, gbeta;
+    float *feat;                   // [np][16] raw features (NULL: not stored)
+    float *aux;                    // [np][4] slip s and T_f
+    uint16_t *xbf;                 // [np][16] normalised BF16 features for the network (NULL: not stored)
+    const float *norm;             // mean[16], std[16] of the features
+};
+
+template <int DIM>
+__device__ __forceinline__ void slip_frame(const double *s, double *e1, double *e2, double *e3)
+{
+    const double m = sqrt(s[0] * s[0] + s[1] * s[1] + s[2] * s[2]);
+    if (m > 1e-300) { e1[0] = s[0] / m; e1[1] = s[1] / m; e1[2] = s[2] / m; }
+    else { e1[0] = 0; e1[1] = 0; e1[2] = 0; e1[DIM - 1] = 1; }
+    if (DIM == 2) {
+        e2[0] = -e1[1]; e2[1] = e1[0]; e2[2] = 0;
+        e3[0] = 0; e3[1] = 0; e3[2] = 1;
+        return;
+    }
+    double up[3] = {0, 0, 1};
+    if (fabs(e1[2]) > 0.999) { up[0] = 1; up[2] = 0; }
+    const double d = up[0] * e1[0] + up[1] * e1[1] + up[2] * e1[2];
+    double v[3] = {up[0] - d * e1[0], up[1] - d * e1[1], up[2] - d * e1[2]};
+    const double n = sqrt(v[0] * v[0] + v[1] * v[1] + v[2] * v[2]);
+    e2[0] = v[0] / n; e2[1] = v[1] / n; e2[2] = v[2] / n;
+    e3[0] = e1[1] * e2[2] - e1[2] * e2[1];
+    e3[1] = e1[2] * e2[0] - e1[0] * e2[2];
+    e3[2] = e1[0] * e2[1] - e1[1] * e2[0];
+}
+
+template <int DIM, class SF>
+__global__ __launch_bounds__(FEAT_THREADS) void k_features(FeatArgs<typename SF::T> a)
+{
+    using T = typename SF::T;
+    using C = double;
+    using L = Lat<DIM>;
+    constexpr int NBLK = 1 << DIM;
+    constexpr int TPB = FEAT_THREADS / NBLK;   // threads per block (32 in 3D, 64 in 2D)
+    constexpr int NN = DIM == 3 ? 4 : 6;
+    __shared__ double bsum[NBLK][6];
+    __shared__ double red_phi[FEAT_THREADS / 64];
+    __shared__ double cand_d[FEAT_THREADS * 6];
+    __shared__ int cand_i[FEAT_THREADS * 6];
+    const int p = blockIdx.x, tid = threadIdx.x;
+    if (block_halted(a.lb.err)) return;
+    const DevParticle P = a.part[p];
+    const int nn[3] = {a.lb.nx, a.lb.ny, a.lb.nz};
+    const int b = a.filter;
+    // the 2 blocks per axis around the centre and their interpolation weights
+    int blo[3] = {0, 0, 0};
+    double fr[3] = {0, 0, 0};
+#pragma unroll
+    for (int d = 0; d < DIM; ++d) {
+        const double c = (P.x[d] - 0.5 * (b - 1)) / b;
+        const double fl = floor(c);
+        blo[d] = (int)fl;
+        fr[d] = c - fl;
+    }
+    // (1) raw moments summed per block; block k handled by threads [k TPB, (k+1) TPB)
+    {
+        const int k = tid / TPB, r = tid % TPB;
+        const int kb[3] = {k & 1, (k >> 1) & 1, (k >> 2) & 1};
+        double s[6] = {0, 0, 0, 0, 0, 0};      // rho - 1, j, S - T_ref, count
+        int nb = 1;
+        for (int d = 0; d < DIM; ++d) nb *= b;
+        for (int o = r; o < nb; o += TPB) {
+            int c[3] = {0, 0, 0};
+            int oo = o;
+            bool ok = true;
+#pragma unroll
+            for (int d = 0; d < DIM; ++d) {
+                int v = (blo[d] + kb[d]) * b + oo % b;
+                oo /= b;
+                if (a.lb.per[d]) { v %= nn[d]; if (v < 0) v += nn[d]; }
+                else if (v < 0 || v >= nn[d]) ok = false;
+                c[d] = v;
+            }
+            if (!ok) continue;
+            T f[L::Q];
+            C g[L::QG];
+            pull<DIM, SF, T, C>(a.lb, c[0], c[1], c[2], f, g);
+            C drho, j[3], dS;
+            moments<DIM, C>(f, g, drho, j, dS);
+            s[0] += drho; s[1] += j[0]; s[2] += j[1]; s[3] += j[2]; s[4] += dS; s[5] += 1.0;
+        }
+        // fixed-order butterfly within the TPB-thread group
+#pragma unroll
+        for (int off = TPB / 2; off; off >>= 1)
+#pragma unroll
+            for (int q = 0; q < 6; ++q) s[q] += __shfl_xor(s[q], off);
+        if (r == 0)
+#pragma unroll
+            for (int q = 0; q < 6; ++q) bsum[k][q] = s[q];
+    }
+    // (2) neighbour scan: per-thread nearest NN by (distance, index), solid volume within 2 D
+    const double D = 2.0 * P.R, rphi = 2.0 * D;
+    double bd[6];
+    int bi[6];
+#pragma unroll
+    for (int q = 0; q < 6; ++q) { bd[q] = 1e300; bi[q] = 0x7fffffff; }
+    double vol = 0.0;
+    for (int jn = tid; jn < a.np; jn += FEAT_THREADS) {
+        const DevParticle Q = a.part[jn];
+        double d2 = 0.0;
+#pragma unroll
+        for (int d = 0; d < DIM; ++d) {
+            double dx = Q.x[d] - P.x[d];
+            if (a.lb.per[d]) dx -= nn[d] * rint(dx / nn[d]);
+            d2 += dx * dx;
+        }
+        if (d2 < rphi * rphi)
+            vol += DIM == 3 ? (4.0 / 3.0) * M_PI * Q.R * Q.R * Q.R : M_PI * Q.R * Q.R;
+        if (jn == p) continue;
+        // insert into the sorted list (distance, then index)
+        if (d2 < bd[NN - 1] || (d2 == bd[NN - 1] && jn < bi[NN - 1])) {
+            int q = NN - 1;
+            while (q > 0 && (d2 < bd[q - 1] || (d2 == bd[q - 1] && jn < bi[q - 1]))) {
+                bd[q] = bd[q - 1]; bi[q] = bi[q - 1];
+                --q;
+            }
+            bd[q] = d2; bi[q] = jn;
+        }
+    }
+#pragma unroll
+    for (int off = 32; off; off >>= 1) vol += __shfl_xor(vol, off);
+    if ((tid & 63) == 0) red_phi[tid >> 6] = vol;
+#pragma unroll
+    for (int q = 0; q < NN; ++q) { cand_d[tid * NN + q] = bd[q]; cand_i[tid * NN + q] = bi[q]; }
+    __syncthreads();
+    if (tid != 0) return;
+    // merge the candidates (thread 0, fixed order)
+    double nd[6];
+    int ni[6];
+#pragma unroll
+    for (int q = 0; q < 6; ++q) { nd[q] = 1e300; ni[q] = 0x7fffffff; }
+    for (int c2 = 0; c2 < FEAT_THREADS * NN; ++c2) {
+        const double d2 = cand_d[c2];
+        const int jn = cand_i[c2];
+        if (d2 < nd[NN - 1] || (d2 == nd[NN - 1] && jn < ni[NN - 1])) {
+            int q = NN - 1;
+            while (q > 0 && (d2 < nd[q - 1] || (d2 == nd[q - 1] && jn < ni[q - 1]))) {
+                nd[q] = nd[q - 1]; ni[q] = ni[q - 1];
+                --q;
+            }
+            nd[q] = d2; ni[q] = jn;
+        }
+    }
+    double vtot = 0.0;
+    for (int w = 0; w < FEAT_THREADS / 64; ++w) vtot += red_phi[w];
+    // (3) fluid at the centre
+    double m[5] = {0, 0, 0, 0, 0};
+    for (int k = 0; k < NBLK; ++k) {
+        double wk = 1.0;
+#pragma unroll
+        for (int d = 0; d < DIM; ++d) wk *= ((k >> d) & 1) ? fr[d] : 1.0 - fr[d];
+        const double cnt = bsum[k][5];
+        if (cnt > 0) {
+            const double rho = cnt + bsum[k][0];
+            m[0] += wk * bsum[k][1] / rho;
+            m[1] += wk * bsum[k][2] / rho;
+            m[2] += wk * bsum[k][3] / rho;
+            m[3] += wk * bsum[k][4] / cnt;
+            m[4] += wk;
+        }
+    }
+    const double inv = m[4] > 0 ? 1.0 / m[4] : 0.0;
+    const double Uf[3] = {m[0] * inv, m[1] * inv, DIM == 3 ? m[2] * inv : 0.0};
+    const double Tf = a.lb.Tref + m[3] * inv;
+    double s[3] = {Uf[0] - P.u[0], Uf[1] - P.u[1], DIM == 3 ? Uf[2] - P.u[2] : 0.0};
+    double e1[3], e2[3], e3[3];
+    slip_frame<DIM>(s, e1, e2, e3);
+    const double smag = sqrt(s[0] * s[0] + s[1] * s[1] + s[2] * s[2]);
+    const double dT = P.T - Tf;
+    double x[16];
+    x[0] = smag * D / a.nu;
+    x[1] = a.gbeta * dT * D * D * D / (a.nu * a.nu);
+    x[2] = vtot / (DIM == 3 ? (4.0 / 3.0) * M_PI * rphi * rphi * rphi : M_PI * rphi * rphi);
+    x[3] = dT;
+    for (int q = 0; q < NN; ++q) {
+        double o[3] = {4.0, 4.0, 4.0};
+        if (ni[q] != 0x7fffffff) {
+            double dx[3] = {0, 0, 0};
+#pragma unroll
+            for (int d = 0; d < DIM; ++d) {
+                dx[d] = a.part[ni[q]].x[d] - P.x[d];
+                if (a.lb.per[d]) dx[d] -= nn[d] * rint(dx[d] / nn[d]);
+            }
+            o[0] = (dx[0] * e1[0] + dx[1] * e1[1] + dx[2] * e1[2]) / D;
+            o[1] = (dx[0] * e2[0] + dx[1] * e2[1] + dx[2] * e2[2]) / D;
+            o[2] = (dx[0] * e3[0] + dx[1] * e3[1] + dx[2] * e3[2]) / D;
+        }
+        if (DIM == 3) { x[4 + 3 * q] = o[0]; x[5 + 3 * q] = o[1]; x[6 + 3 * q] = o[2]; }
+        else { x[4 + 2 * q] = o[0]; x[5 + 2 * q] = o[1]; }
+    }
+    if (a.feat)
+        for (int q = 0; q < 16; ++q) a.feat[(size_t)p * 16 + q] = (float)x[q];
+    if (a.xbf)
+        for (int q = 0; q < 16; ++q) {
+            const float v = (float)((x[q] - (double)a.norm[q]) / (double)a.norm[16 + q]);
+            const uint32_t u = __float_as_uint(v);
+            const uint32_t r = (u & 0x7fffffffu) > 0x7f800000u ? (u | 0x00400000u) : u + 0x7fffu + ((u >> 16) & 1u);
+            a.xbf[(size_t)p * 16 + q] = (uint16_t)(r >> 16);
+        }
+    a.aux[(size_t)p * 4 + 0] = (float)s[0];
+    a.aux[(size_t)p * 4 + 1] = (float)s[1];
+    a.aux[(size_t)p * 4 + 2] = (float)s[2];
+    a.aux[(size_t)p * 4 + 3] = (float)Tf;
+}
+
+// Targets of the current state: the reactions of the resolved exchange in
+// the slip frame that k_features stored (see above).
+template <int DIM>
+__global__ void k_targets(const DevParticle *part, int np, const DevReact *react, const float *aux, double nu,
+                          double alpha, float *targ)
+{
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= np) return;
+    double s[3] = {aux[(size_t)p * 4], aux[(size_t)p * 4 + 1], aux[(size_t)p * 4 + 2]};
+    double e1[3], e2[3], e3[3];
+    slip_frame<DIM>(s, e1, e2, e3);
+    const DevReact R = react[p];
+    const double f2 = nu * nu, D = 2.0 * part[p].R;
+    targ[(size_t)p * 4 + 0] = (float)((R.F[0] * e1[0] + R.F[1] * e1[1] + R.F[2] * e1[2]) / f2);
+    targ[(size_t)p * 4 + 1] = (float)((R.F[0] * e2[0] + R.F[1] * e2[1] + R.F[2] * e2[2]) / f2);
+    targ[(size_t)p * 4 + 2] = DIM == 3 ? (float)((R.F[0] * e3[0] + R.F[1] * e3[1] + R.F[2] * e3[2]) / f2) : 0.f;
+    targ[(size_t)p * 4 + 3] = (float)(R.H / (M_PI * (DIM == 3 ? D : 1.0) * alpha));
+}
+
+// The learned closure in the coarse one-point mode: the network's outputs
+// (normalised targets) become the hydrodynamic force and heat of each
+// particle; its one point carries their reactions to the fluid (F_l A_l =
+// -F, Q_l A_l = H) and the DEM receives F and no fluid torque (a point has
+// no lever arm).
+template <int DIM, class T>
+__global__ void k_closure(const DevParticle *part, int np, const float *y, const float *norm, const float *aux,
+                          double nu, double alpha, MarkerRec<T> *mk, DevReact *react, const int *err)
+{
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= np || halted(err)) return;
+    const DevParticle P = part[p];
+    double yv[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) yv[q] = (double)y[(size_t)p * 4 + q] * (double)norm[36 + q] + (double)norm[32 + q];
+    double s[3] = {aux[(size_t)p * 4], aux[(size_t)p * 4 + 1], aux[(size_t)p * 4 + 2]};
+    double e1[3], e2[3], e3[3];
+    slip_frame<DIM>(s, e1, e2, e3);
+    const double D = 2.0 * P.R, f2 = nu * nu;
+    double F[3];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) F[c] = (yv[0] * e1[c] + yv[1] * e2[c] + (DIM == 3 ? yv[2] * e3[c] : 0.0)) * f2;
+    if (DIM == 2) F[2] = 0.0;
+    const double H = yv[3] * M_PI * (DIM == 3 ? D : 1.0) * alpha;
+    MarkerRec<T> rec;
+    double r[3], U[3], tt[3];
+    marker_setup<DIM, T>(P, make_double4(0.0, 0.0, 0.0, 0.0), r, U, rec, tt);
+#pragma unroll
+    for (int c = 0; c < 3; ++c) rec.fa[c] = (T)(-F[c]);
+    rec.qa = (T)H;
+    mk[p] = rec;
+    DevReact R;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) { R.F[c] = F[c]; R.tq[c] = 0.0; }
+    R.H = H;
+    R.dTA = 0.5 * H;
+    react[p] = R;
+}
+
 // --------------------------------------------------------------------------
 // K3: bin particles into lattice tiles (integer counting sort).  A particle
 // lands in every tile its markers' spreading footprints can touch: nodes

@@ -32,6 +32,7 @@
 #include <vector>
 
 #include "../../include/pibm.h"
+#include "pibm_internal.h"
 
 namespace {
 
@@ -429,6 +430,19 @@ int mlp_loss(pibm_mlp *m, int n, double *loss)
 
 }  // namespace
 
+int pibm_mlp_forward_on(pibm_mlp *m, const void *dev_x, float *dev_y, int n, hipStream_t stream)
+{
+    if (!m || n < 0 || (n > 0 && (!dev_x || !dev_y))) return PIBM_EINVAL;
+    if (((uintptr_t)dev_x & 7) || ((uintptr_t)dev_y & 15)) return PIBM_EINVAL;
+    if (n == 0) return PIBM_OK;
+    const int ntile = (n + 15) / 16;
+    int grid = (ntile + 3) / 4;
+    if (grid > 2048) grid = 2048;
+    MlpArgs a{m->param, m->wbf};
+    hipLaunchKernelGGL(k_mlp_fwd, dim3(grid), dim3(MLP_THREADS), 0, stream, a, (const uint16_t *)dev_x, dev_y, n);
+    return hipGetLastError() == hipSuccess ? PIBM_OK : PIBM_EDEVICE;
+}
+
 extern "C" {
 
 size_t pibm_mlp_workspace_bytes(int max_batch)
@@ -487,15 +501,8 @@ int pibm_mlp_get_params(pibm_mlp *m, float *host_params)
 
 int pibm_mlp_forward(pibm_mlp *m, const void *dev_x, float *dev_y, int n)
 {
-    if (!m || n < 0 || (n > 0 && (!dev_x || !dev_y))) return PIBM_EINVAL;
-    if (((uintptr_t)dev_x & 7) || ((uintptr_t)dev_y & 15)) return PIBM_EINVAL;
-    if (n == 0) return PIBM_OK;
-    const int ntile = (n + 15) / 16;
-    int grid = (ntile + 3) / 4;
-    if (grid > 2048) grid = 2048;
-    MlpArgs a{m->param, m->wbf};
-    hipLaunchKernelGGL(k_mlp_fwd, dim3(grid), dim3(MLP_THREADS), 0, m->stream, a, (const uint16_t *)dev_x, dev_y, n);
-    return hipGetLastError() == hipSuccess ? PIBM_OK : PIBM_EDEVICE;
+    if (!m) return PIBM_EINVAL;
+    return pibm_mlp_forward_on(m, dev_x, dev_y, n, m->stream);
 }
 
 int pibm_mlp_grads(pibm_mlp *m, const void *dev_x, const float *dev_t, int n, float *host_grads, double *loss)

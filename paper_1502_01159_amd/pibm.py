@@ -27,6 +27,7 @@ EXPORTS = [
     "pibm_profile", "pibm_profile_read",
     "pibm_mlp_workspace_bytes", "pibm_mlp_create", "pibm_mlp_set_params", "pibm_mlp_get_params",
     "pibm_mlp_forward", "pibm_mlp_grads", "pibm_mlp_train_step", "pibm_mlp_destroy",
+    "pibm_features", "pibm_set_closure",
 ]
 MLP_IN, MLP_HIDDEN, MLP_OUT, MLP_NPARAM = 16, 128, 4, 35716
 PHASES = ("markers", "bin", "lattice", "dem")
@@ -104,6 +105,8 @@ def lib():
         L.pibm_mlp_grads.argtypes = [vp, vp, vp, ctypes.c_int, fp, dp]
         L.pibm_mlp_train_step.argtypes = [vp, vp, vp, ctypes.c_int, ctypes.c_float, dp]
         L.pibm_mlp_destroy.argtypes = [vp]
+        L.pibm_features.argtypes = [vp, ctypes.c_int, fp, fp]
+        L.pibm_set_closure.argtypes = [vp, vp, fp]
         _lib = L
     return _lib
 
@@ -257,6 +260,31 @@ class Simulation:
     def set_particles(self, P):
         arr = make_particles(P)
         self._check(lib().pibm_set_particles(self._h, arr, len(P)), "pibm_set_particles")
+
+    def features(self, filter: int):
+        """Closure features (n, 16) and targets (n, 4) of the current state."""
+        x = np.empty((self.np, 16), dtype=np.float32)
+        t = np.empty((self.np, 4), dtype=np.float32)
+        fp = ctypes.POINTER(ctypes.c_float)
+        st = lib().pibm_features(self._h, int(filter), x.ctypes.data_as(fp), t.ctypes.data_as(fp))
+        if st != OK:
+            raise PibmError(st, "pibm_features")
+        return x, t
+
+    def set_closure(self, mlp, norm=None):
+        """Use the network `mlp` (an :class:`Mlp`) in the one-point mode;
+        norm = 40 floats (feature mean, std, target mean, std).  None restores
+        the point exchange."""
+        if mlp is None:
+            st = lib().pibm_set_closure(self._h, None, None)
+        else:
+            norm = np.ascontiguousarray(norm, dtype=np.float32)
+            if norm.size != 40:
+                raise ValueError("norm must hold 40 values")
+            self._closure = (mlp, norm)
+            st = lib().pibm_set_closure(self._h, mlp._h, norm.ctypes.data_as(ctypes.POINTER(ctypes.c_float)))
+        if st != OK:
+            raise PibmError(st, "pibm_set_closure")
 
     def fields(self, check: bool = True):
         rho = np.empty(self.N)

@@ -3,7 +3,7 @@ identical seeded inputs.
 
 Tolerances:
 * FP64 storage: populations / fields / reactions to 1e-11 relative (the only
-  differences are summation order and the 2^-48 fixed-point spreading);
+  differences are summation order and the 2^-50 fixed-point spreading);
 * FP32 storage: max relative field error <= 1e-5 after 1000 steps for rho,
   u (normalised by max |u|) and T; particle positions <= 1e-4 lattice units;
 * FP16 / BF16 deviation storage: reported per field, bounded as stated below.
