@@ -238,29 +238,33 @@ int pibm_mlp_destroy(pibm_mlp *m);
 /* Closure features and targets of the current state (not advanced), one row
  * per particle, host arrays x[n_particles][16] and t[n_particles][4] (either
  * may be NULL).  The fluid seen by a particle is the raw moments (rho, j, S)
- * averaged over blocks of filter^d nodes (filter = 4 on a resolved lattice,
- * 1 on a coarse one) and interpolated linearly at its centre; with the slip
+ * summed over the nodes of the shell 0.75 D <= |x - X_p| <= 1.5 D around it,
+ * U_f = sum j / sum rho, T_f = mean S (a region in units of D: the same on a
+ * resolved and on a coarsened lattice); with the slip
  * s = U_f - U_p and its frame e1 = s/|s|, e2 = the up axis made normal to e1,
  * e3 = e1 x e2 (2D: e2 = e1 turned by +90 degrees):
  *   x = Re_p = |s| D/nu, Gr_p = g beta (T_p - T_f) D^3/nu^2, phi (solid
  *       volume of the particles with centres within 2 D over that ball),
  *       T_p - T_f, then the offsets of the 4 nearest centres in (e1, e2, e3)
  *       over D (2D: 6 nearest, 2 components), missing ones at 4;
- *   t = (F.e1, F.e2, F.e3) / (rho0 nu^2) and H / (pi D alpha) (2D:
- *       H / (pi alpha)), from the Lagrangian-point exchange of Sec. 2.2
- *       evaluated on this state (Eqs. lbm7-lbm8, lbm13); that exchange's
- *       reactions replace the last step's in pibm_particles.
+ *   t = (F.e1, F.e2, F.e3) / (3 pi nu D |s|) (drag and lift over the
+ *       Stokes drag of the slip; 2D: third entry 0) and the Nusselt number
+ *       H / (pi D alpha (T_p - T_f)) (2D: H / (pi alpha (T_p - T_f))), 0 where
+ *       |s| or T_p - T_f vanishes, from the Lagrangian-point exchange of
+ *       Sec. 2.2 evaluated on this state (Eqs. lbm7-lbm8, lbm13); that
+ *       exchange's reactions replace the last step's in pibm_particles.
  * Synchronises. */
-int pibm_features(pibm_ctx *ctx, int filter, float *x, float *t);
+int pibm_features(pibm_ctx *ctx, float *x, float *t);
 
 /* Coarse one-point mode (PIBM_MARKERS_POINT only): replace the point
  * exchange by the network m (borrowed, on the same device).  Each step the
- * particle's features (filter 1) are normalised with norm[0..15] (mean) and
+ * particle's features are normalised with norm[0..15] (mean) and
  * norm[16..31] (std > 0), the network's outputs denormalised with
- * norm[32..35] (mean) and norm[36..39] (std > 0), and the resulting force F
- * and heat H act on the particle (no fluid torque) while -F and H are spread
- * to the fluid from its centre with the kernel of Eq. (lbm12).  m = NULL
- * restores the point exchange. */
+ * norm[32..35] (mean) and norm[36..39] (std > 0) into the targets above,
+ * and the force F = (t0 e1 + t1 e2 + t2 e3) 3 pi nu D |s| and heat
+ * H = t3 pi D alpha (T_p - T_f) act on the particle (no fluid torque) while
+ * -F and H are spread to the fluid from its centre with the kernel of
+ * Eq. (lbm12).  m = NULL restores the point exchange. */
 int pibm_set_closure(pibm_ctx *ctx, pibm_mlp *m, const float *norm);
 
 /* Static description of a status code. */

@@ -6,11 +6,10 @@ neighbours by full search) to check the GPU kernels; only tests/ and the
 benchmark's CPU leg import it.  It shares no code with the HIP library.
 
 Definitions (one row per particle, D = 2R):
-  fluid seen: rho, j, S summed over blocks of b^d nodes (block I covers nodes
-    b I .. b I + b - 1 per axis; wrapped on periodic axes, nodes outside a
-    wall dropped), u_blk = sum j / sum rho, T_blk = sum S / count, then
-    linear interpolation between the 2^d block centres b I + (b - 1)/2
-    around the particle centre, renormalised over blocks that hold nodes;
+  fluid seen: rho, j, S summed over the lattice nodes x with
+    0.75 D <= |x - X_p| <= 1.5 D (coordinates unwrapped, then wrapped on
+    periodic axes; nodes beyond a wall dropped), U_f = sum j / sum rho,
+    T_f = sum S / count;
   slip s = U_f - U_p; e1 = s/|s| (|s| = 0: the up axis); 3D: e2 = the up
     axis z (x if |e1_z| > 0.999) minus its e1 part, normalised, e3 = e1 x e2;
     2D: e2 = (-e1_y, e1_x);
@@ -19,7 +18,9 @@ Definitions (one row per particle, D = 2R):
        e2), missing ones at 4], phi = volume (area) of the particles whose
        centres are within 2D (minimum image), self included, over the ball
        (disk) of radius 2D;
-  t = [F.e1, F.e2, F.e3 (2D: 0)] / nu^2, H / (pi D alpha) (2D: H/(pi alpha)).
+  t = [F.e1, F.e2, F.e3 (2D: 0)] / (3 pi nu D |s|) and the Nusselt number
+      H / (pi D alpha (T_p - T_f)) (2D: H / (pi alpha (T_p - T_f))), 0 where
+      |s| or T_p - T_f is 0.
 """
 from __future__ import annotations
 
@@ -39,7 +40,7 @@ def slip_frame(s, dim):
     return e1, e2, np.cross(e1, e2)
 
 
-def features(rho, j, S, shape, per, P, b, nu, gbeta, dim):
+def features(rho, j, S, shape, per, P, nu, gbeta, dim):
     """rho (N), j (N, 3), S (N) absolute raw moments on a lattice of
     shape (nz, ny, nx); P particle rows (x[3], u[3], ..., R at 12, T at 14 of
     the 16-column particle state).  Returns (x (n, 16), slips (n, 3), T_f)."""
@@ -58,46 +59,32 @@ def features(rho, j, S, shape, per, P, b, nu, gbeta, dim):
         Up = P[p, 3:6]
         R, Tp = P[p, 12], P[p, 14]
         D = 2 * R
-        lo, fr = [0, 0, 0], [0.0, 0.0, 0.0]
-        for d in range(dim):
-            v = (c[d] - 0.5 * (b - 1)) / b
-            lo[d] = math.floor(v)
-            fr[d] = v - lo[d]
-        acc = np.zeros(4)
-        wsum = 0.0
-        for k in range(1 << dim):
-            kb = [(k >> d) & 1 for d in range(3)]
-            w = 1.0
-            for d in range(dim):
-                w *= fr[d] if kb[d] else 1 - fr[d]
-            sr, sj, sS, cnt = 0.0, np.zeros(3), 0.0, 0
-            ranges = []
-            for d in range(3):
-                if d >= dim:
-                    ranges.append([0])
+        r_in, r_out = 0.75 * D, 1.5 * D
+        axes = []
+        for d in range(3):
+            if d >= dim:
+                axes.append([(0, 0.0)])
+                continue
+            vals = []
+            for v0 in range(math.ceil(c[d] - r_out), math.floor(c[d] + r_out) + 1):
+                v = v0 % nn[d] if per[d] else v0
+                if not per[d] and (v < 0 or v >= nn[d]):
                     continue
-                idx = []
-                for o in range(b):
-                    v = (lo[d] + kb[d]) * b + o
-                    if per[d]:
-                        v %= nn[d]
-                    elif v < 0 or v >= nn[d]:
+                vals.append((v, (v0 - c[d]) ** 2))
+            axes.append(vals)
+        sr, sj, sS, cnt = 0.0, np.zeros(3), 0.0, 0
+        for z, dz in axes[2]:
+            for y, dy in axes[1]:
+                for x, dx in axes[0]:
+                    r2 = dx + dy + dz
+                    if r2 < r_in * r_in or r2 > r_out * r_out:
                         continue
-                    idx.append(v)
-                ranges.append(idx)
-            for z in ranges[2]:
-                for y in ranges[1]:
-                    for x in ranges[0]:
-                        sr += rho[z, y, x]
-                        sj += jj[z, y, x]
-                        sS += SS[z, y, x]
-                        cnt += 1
-            if cnt:
-                acc[:3] += w * sj / sr
-                acc[3] += w * sS / cnt
-                wsum += w
-        Uf = acc[:3] / wsum
-        Tf = acc[3] / wsum
+                    sr += rho[z, y, x]
+                    sj += jj[z, y, x]
+                    sS += SS[z, y, x]
+                    cnt += 1
+        Uf = sj / sr
+        Tf = sS / cnt
         if dim == 2:
             Uf[2] = 0.0
         s = Uf - Up
@@ -141,12 +128,17 @@ def features(rho, j, S, shape, per, P, b, nu, gbeta, dim):
     return X, slips, Tfs
 
 
-def targets(F, H, slips, R, nu, alpha, dim):
+def targets(F, H, slips, R, dT, nu, alpha, dim):
     t = np.zeros((len(F), 4))
     for p in range(len(F)):
         e1, e2, e3 = slip_frame(slips[p], dim)
-        t[p, 0] = F[p].dot(e1) / nu ** 2
-        t[p, 1] = F[p].dot(e2) / nu ** 2
-        t[p, 2] = F[p].dot(e3) / nu ** 2 if dim == 3 else 0.0
-        t[p, 3] = H[p] / (math.pi * (2 * R[p] if dim == 3 else 1.0) * alpha)
+        D = 2 * R[p]
+        fs = 3 * math.pi * nu * D * np.linalg.norm(slips[p])
+        hs = math.pi * (D if dim == 3 else 1.0) * alpha * dT[p]
+        f = 1.0 / fs if fs > 1e-300 else 0.0
+        h = 1.0 / hs if abs(hs) > 1e-300 else 0.0
+        t[p, 0] = F[p].dot(e1) * f
+        t[p, 1] = F[p].dot(e2) * f
+        t[p, 2] = F[p].dot(e3) * f if dim == 3 else 0.0
+        t[p, 3] = H[p] * h
     return t

@@ -395,7 +395,7 @@ int launch_markers(pibm_ctx *c, bool reactions)
 }
 
 template <int DIM, class SF>
-int launch_features(pibm_ctx *c, int filter, bool raw, bool for_network)
+int launch_features(pibm_ctx *c, bool raw, bool for_network)
 {
     using T = typename SF::T;
     if (c->P.np == 0) return PIBM_OK;
@@ -403,7 +403,6 @@ int launch_features(pibm_ctx *c, int filter, bool raw, bool for_network)
     f.lb = lbm_args<T>(c);
     f.part = (const DevParticle *)c->r(c->pcur ? R_PART1 : R_PART0);
     f.np = c->P.np;
-    f.filter = filter;
     f.nu = c->d.nu;
     f.alpha = c->d.alpha;
     f.gbeta = c->d.gbeta;
@@ -423,7 +422,7 @@ int launch_closure(pibm_ctx *c)
     using T = typename SF::T;
     if (c->P.np == 0) return PIBM_OK;
     int st;
-    if ((st = launch_features<DIM, SF>(c, 1, false, true))) return st;
+    if ((st = launch_features<DIM, SF>(c, false, true))) return st;
     if ((st = pibm_mlp_forward_on(c->closure, c->r(R_XBF), (float *)c->r(R_YMLP), c->P.np, c->stream))) return st;
     hipLaunchKernelGGL((k_closure<DIM, T>), dim3((c->P.np + 127) / 128), dim3(128), 0, c->stream,
                        (const DevParticle *)c->r(c->pcur ? R_PART1 : R_PART0), c->P.np, (const float *)c->r(R_YMLP),
@@ -610,17 +609,17 @@ template <int DIM, class SF> struct StepOp { static int run(pibm_ctx *c, int n) 
 // Features of the current state, the resolved exchange's reactions for it,
 // and the targets in the same slip frame.
 template <int DIM, class SF>
-int features_impl(pibm_ctx *c, int filter)
+int features_impl(pibm_ctx *c)
 {
     int st;
-    if ((st = launch_features<DIM, SF>(c, filter, true, false))) return st;
+    if ((st = launch_features<DIM, SF>(c, true, false))) return st;
     if ((st = launch_markers<DIM, SF>(c, true))) return st;
     hipLaunchKernelGGL((k_targets<DIM>), dim3((c->P.np + 127) / 128), dim3(128), 0, c->stream,
                        (const DevParticle *)c->r(c->pcur ? R_PART1 : R_PART0), c->P.np, (const DevReact *)c->r(R_REACT),
                        (const float *)c->r(R_AUX), c->d.nu, c->d.alpha, (float *)c->r(R_TARG));
     return hip_ok(c, hipGetLastError());
 }
-template <int DIM, class SF> struct FeatOp { static int run(pibm_ctx *c, int filter) { return features_impl<DIM, SF>(c, filter); } };
+template <int DIM, class SF> struct FeatOp { static int run(pibm_ctx *c) { return features_impl<DIM, SF>(c); } };
 template <int DIM, class SF> struct MacroOp { static int run(pibm_ctx *c) { return macro_impl<DIM, SF>(c); } };
 template <int DIM, class SF> struct InitOp {
     static int run(pibm_ctx *c) {
@@ -844,13 +843,13 @@ int pibm_fields(pibm_ctx *c, double *rho, double *u, double *T)
     return st;
 }
 
-int pibm_features(pibm_ctx *c, int filter, float *x, float *t)
+int pibm_features(pibm_ctx *c, float *x, float *t)
 {
-    if (!c || filter < 1 || filter > 16) return PIBM_EINVAL;
+    if (!c) return PIBM_EINVAL;
     if (c->device_lost) return PIBM_EDEVICE;
     if (c->sticky) return c->sticky;
     if (c->P.np == 0) return PIBM_OK;
-    int st = dispatch<FeatOp>(c, filter);
+    int st = dispatch<FeatOp>(c);
     if (st) return st;
     const size_t np = (size_t)c->P.np;
     hipError_t e = hipSuccess;

@@ -993,9 +993,10 @@ __global__ __launch_bounds__(256) void k_markers(MkArgs<typename SF::T> a)
 // outputs; not in the paper).  All dimensionless, so that they carry over
 // from a resolved lattice to one coarsened by diffusive scaling:
 //   fluid seen by the particle: the raw moments (rho, j, S, no forcing terms)
-//     averaged over blocks of b^d nodes, linearly interpolated between the
-//     2^d block centres around the particle centre (b = 4 on a resolved
-//     lattice, b = 1 on a coarse one);
+//     summed over the nodes of the shell 0.75 D <= |x - X_p| <= 1.5 D (a
+//     shell in units of D, so the same region on a resolved and on a coarse
+//     lattice; inside the body the PIBM fluid moves with the particle and
+//     takes its temperature), U_f = sum j / sum rho, T_f = mean S;
 //   slip s = U_f - U_p and its frame e1 = s/|s|, e2 = the up axis made
 //     normal to e1 (x if s is nearly vertical), e3 = e1 x e2 (2D: e2 = e1
 //     turned by +90 degrees);
@@ -1003,9 +1004,13 @@ __global__ __launch_bounds__(256) void k_markers(MkArgs<typename SF::T> a)
 //        T_p - T_f, offsets of the 4 (2D: 6) nearest centres in the frame / D
 //        (missing neighbours at 4, 4, 4)], phi = solid volume (area) of the
 //        particles whose centres lie within 2 D, over that ball (disk);
-//   t = [F.e1, F.e2, F.e3 (2D: 0)] / (rho0 nu^2) and H / (pi D alpha) in 3D,
-//       H / (pi alpha) per unit depth in 2D, from the last step's reactions.
-// One workgroup (256 threads) per particle; block sums reduced in a fixed
+//   t = [F.e1, F.e2, F.e3 (2D: 0)] / (3 pi nu D |s|) (drag and lift over the
+//       Stokes drag of the slip) and the Nusselt number H / (pi D alpha
+//       (T_p - T_f)) in 3D, H / (pi alpha (T_p - T_f)) per unit depth in 2D
+//       (0 where |s| or T_p - T_f vanishes), from the point exchange's
+//       reactions; the closure inverts these, so its force vanishes with the
+//       slip and its heat with the temperature difference.
+// One workgroup (256 threads) per particle; shell sums reduced in a fixed
 // order; neighbours by a full scan with ties broken by index.
 // --------------------------------------------------------------------------
 constexpr int FEAT_THREADS = 256;
@@ -1014,7 +1019,7 @@ constexpr int FEAT_NB = 4;                      // neighbours kept (3D); 2D keep
 template <typename T> struct FeatArgs {
     LbmArgs<T> lb;
     const DevParticle *part;
-    int np, filter;
+    int np;
     double nu, alpha, gbeta;
     float *feat;                   // [np][16] raw features (NULL: not stored)
     float *aux;                    // [np][4] slip s and T_f
@@ -1050,10 +1055,8 @@ __global__ __launch_bounds__(FEAT_THREADS) void k_features(FeatArgs<typename SF:
     using T = typename SF::T;
     using C = double;
     using L = Lat<DIM>;
-    constexpr int NBLK = 1 << DIM;
-    constexpr int TPB = FEAT_THREADS / NBLK;   // threads per block (32 in 3D, 64 in 2D)
     constexpr int NN = DIM == 3 ? 4 : 6;
-    __shared__ double bsum[NBLK][6];
+    __shared__ double ssum[FEAT_THREADS / 64][6];
     __shared__ double red_phi[FEAT_THREADS / 64];
     __shared__ double cand_d[FEAT_THREADS * 6];
     __shared__ int cand_i[FEAT_THREADS * 6];
@@ -1061,55 +1064,59 @@ __global__ __launch_bounds__(FEAT_THREADS) void k_features(FeatArgs<typename SF:
     if (block_halted(a.lb.err)) return;
     const DevParticle P = a.part[p];
     const int nn[3] = {a.lb.nx, a.lb.ny, a.lb.nz};
-    const int b = a.filter;
-    // the 2 blocks per axis around the centre and their interpolation weights
-    int blo[3] = {0, 0, 0};
-    double fr[3] = {0, 0, 0};
+    const double D = 2.0 * P.R;
+    const double r_in = 0.75 * D, r_out = 1.5 * D;
+    // (1) raw moments summed over the shell's nodes, a fixed share per thread
+    int lo[3] = {0, 0, 0}, ext[3] = {1, 1, 1};
 #pragma unroll
     for (int d = 0; d < DIM; ++d) {
-        const double c = (P.x[d] - 0.5 * (b - 1)) / b;
-        const double fl = floor(c);
-        blo[d] = (int)fl;
-        fr[d] = c - fl;
+        lo[d] = (int)ceil(P.x[d] - r_out);
+        ext[d] = (int)floor(P.x[d] + r_out) - lo[d] + 1;
     }
-    // (1) raw moments summed per block; block k handled by threads [k TPB, (k+1) TPB)
-    {
-        const int k = tid / TPB, r = tid % TPB;
-        const int kb[3] = {k & 1, (k >> 1) & 1, (k >> 2) & 1};
-        double s[6] = {0, 0, 0, 0, 0, 0};      // rho - 1, j, S - T_ref, count
-        int nb = 1;
-        for (int d = 0; d < DIM; ++d) nb *= b;
-        for (int o = r; o < nb; o += TPB) {
-            int c[3] = {0, 0, 0};
-            int oo = o;
-            bool ok = true;
+    bool sane = true;
 #pragma unroll
-            for (int d = 0; d < DIM; ++d) {
-                int v = (blo[d] + kb[d]) * b + oo % b;
-                oo /= b;
-                if (a.lb.per[d]) { v %= nn[d]; if (v < 0) v += nn[d]; }
-                else if (v < 0 || v >= nn[d]) ok = false;
-                c[d] = v;
-            }
-            if (!ok) continue;
-            T f[L::Q];
-            C g[L::QG];
-            pull<DIM, SF, T, C>(a.lb, c[0], c[1], c[2], f, g);
-            C drho, j[3], dS;
-            moments<DIM, C>(f, g, drho, j, dS);
-            s[0] += drho; s[1] += j[0]; s[2] += j[1]; s[3] += j[2]; s[4] += dS; s[5] += 1.0;
+    for (int d = 0; d < DIM; ++d) sane = sane && ext[d] >= 1 && ext[d] <= 4096;
+    const int nbox = sane ? ext[0] * ext[1] * ext[2] : 0;   // non-finite centre: empty shell
+    double sm[5] = {0, 0, 0, 0, 0};               // rho, j, S - T_ref
+    double cnt = 0.0;
+    for (int o = tid; o < nbox; o += FEAT_THREADS) {
+        int c[3] = {0, 0, 0};
+        double r2 = 0.0;
+        bool ok = true;
+        int oo = o;
+#pragma unroll
+        for (int d = 0; d < DIM; ++d) {
+            const int v0 = lo[d] + oo % ext[d];
+            oo /= ext[d];
+            const double dx = v0 - P.x[d];
+            r2 += dx * dx;
+            int v = v0;
+            if (a.lb.per[d]) { v %= nn[d]; if (v < 0) v += nn[d]; }
+            else if (v < 0 || v >= nn[d]) ok = false;
+            c[d] = v;
         }
-        // fixed-order butterfly within the TPB-thread group
+        if (!ok || r2 < r_in * r_in || r2 > r_out * r_out) continue;
+        T f[L::Q];
+        C g[L::QG];
+        pull<DIM, SF, T, C>(a.lb, c[0], c[1], c[2], f, g);
+        C drho, j[3], dS;
+        moments<DIM, C>(f, g, drho, j, dS);
+        sm[0] += 1.0 + drho; sm[1] += j[0]; sm[2] += j[1]; sm[3] += j[2]; sm[4] += dS;
+        cnt += 1.0;
+    }
 #pragma unroll
-        for (int off = TPB / 2; off; off >>= 1)
+    for (int off = 32; off; off >>= 1) {
 #pragma unroll
-            for (int q = 0; q < 6; ++q) s[q] += __shfl_xor(s[q], off);
-        if (r == 0)
+        for (int q = 0; q < 5; ++q) sm[q] += __shfl_xor(sm[q], off);
+        cnt += __shfl_xor(cnt, off);
+    }
+    if ((tid & 63) == 0) {
 #pragma unroll
-            for (int q = 0; q < 6; ++q) bsum[k][q] = s[q];
+        for (int q = 0; q < 5; ++q) ssum[tid >> 6][q] = sm[q];
+        ssum[tid >> 6][5] = cnt;
     }
     // (2) neighbour scan: per-thread nearest NN by (distance, index), solid volume within 2 D
-    const double D = 2.0 * P.R, rphi = 2.0 * D;
+    const double rphi = 2.0 * D;
     double bd[6];
     int bi[6];
 #pragma unroll
@@ -1163,25 +1170,14 @@ __global__ __launch_bounds__(FEAT_THREADS) void k_features(FeatArgs<typename SF:
     }
     double vtot = 0.0;
     for (int w = 0; w < FEAT_THREADS / 64; ++w) vtot += red_phi[w];
-    // (3) fluid at the centre
-    double m[5] = {0, 0, 0, 0, 0};
-    for (int k = 0; k < NBLK; ++k) {
-        double wk = 1.0;
+    // (3) fluid seen by the particle (waves summed in a fixed order)
+    double tot[6] = {0, 0, 0, 0, 0, 0};
+    for (int w = 0; w < FEAT_THREADS / 64; ++w)
 #pragma unroll
-        for (int d = 0; d < DIM; ++d) wk *= ((k >> d) & 1) ? fr[d] : 1.0 - fr[d];
-        const double cnt = bsum[k][5];
-        if (cnt > 0) {
-            const double rho = cnt + bsum[k][0];
-            m[0] += wk * bsum[k][1] / rho;
-            m[1] += wk * bsum[k][2] / rho;
-            m[2] += wk * bsum[k][3] / rho;
-            m[3] += wk * bsum[k][4] / cnt;
-            m[4] += wk;
-        }
-    }
-    const double inv = m[4] > 0 ? 1.0 / m[4] : 0.0;
-    const double Uf[3] = {m[0] * inv, m[1] * inv, DIM == 3 ? m[2] * inv : 0.0};
-    const double Tf = a.lb.Tref + m[3] * inv;
+        for (int q = 0; q < 6; ++q) tot[q] += ssum[w][q];
+    const double irho = tot[0] > 0 ? 1.0 / tot[0] : 0.0;
+    const double Uf[3] = {tot[1] * irho, tot[2] * irho, DIM == 3 ? tot[3] * irho : 0.0};
+    const double Tf = a.lb.Tref + (tot[5] > 0 ? tot[4] / tot[5] : 0.0);
     double s[3] = {Uf[0] - P.u[0], Uf[1] - P.u[1], DIM == 3 ? Uf[2] - P.u[2] : 0.0};
     double e1[3], e2[3], e3[3];
     slip_frame<DIM>(s, e1, e2, e3);
@@ -1235,11 +1231,16 @@ __global__ void k_targets(const DevParticle *part, int np, const DevReact *react
     double e1[3], e2[3], e3[3];
     slip_frame<DIM>(s, e1, e2, e3);
     const DevReact R = react[p];
-    const double f2 = nu * nu, D = 2.0 * part[p].R;
-    targ[(size_t)p * 4 + 0] = (float)((R.F[0] * e1[0] + R.F[1] * e1[1] + R.F[2] * e1[2]) / f2);
-    targ[(size_t)p * 4 + 1] = (float)((R.F[0] * e2[0] + R.F[1] * e2[1] + R.F[2] * e2[2]) / f2);
-    targ[(size_t)p * 4 + 2] = DIM == 3 ? (float)((R.F[0] * e3[0] + R.F[1] * e3[1] + R.F[2] * e3[2]) / f2) : 0.f;
-    targ[(size_t)p * 4 + 3] = (float)(R.H / (M_PI * (DIM == 3 ? D : 1.0) * alpha));
+    const double D = 2.0 * part[p].R;
+    const double smag = sqrt(s[0] * s[0] + s[1] * s[1] + s[2] * s[2]);
+    const double dT = (double)part[p].T - (double)aux[(size_t)p * 4 + 3];
+    const double fs = 3.0 * M_PI * nu * D * smag;             // Stokes drag of the slip
+    const double hs = M_PI * (DIM == 3 ? D : 1.0) * alpha * dT; // conduction scale of the heat
+    const double if_ = fs > 1e-300 ? 1.0 / fs : 0.0, ih = fabs(hs) > 1e-300 ? 1.0 / hs : 0.0;
+    targ[(size_t)p * 4 + 0] = (float)((R.F[0] * e1[0] + R.F[1] * e1[1] + R.F[2] * e1[2]) * if_);
+    targ[(size_t)p * 4 + 1] = (float)((R.F[0] * e2[0] + R.F[1] * e2[1] + R.F[2] * e2[2]) * if_);
+    targ[(size_t)p * 4 + 2] = DIM == 3 ? (float)((R.F[0] * e3[0] + R.F[1] * e3[1] + R.F[2] * e3[2]) * if_) : 0.f;
+    targ[(size_t)p * 4 + 3] = (float)(R.H * ih);
 }
 
 // The learned closure in the coarse one-point mode: the network's outputs
@@ -1260,12 +1261,14 @@ __global__ void k_closure(const DevParticle *part, int np, const float *y, const
     double s[3] = {aux[(size_t)p * 4], aux[(size_t)p * 4 + 1], aux[(size_t)p * 4 + 2]};
     double e1[3], e2[3], e3[3];
     slip_frame<DIM>(s, e1, e2, e3);
-    const double D = 2.0 * P.R, f2 = nu * nu;
+    const double D = 2.0 * P.R;
+    const double fs = 3.0 * M_PI * nu * D * sqrt(s[0] * s[0] + s[1] * s[1] + s[2] * s[2]);
+    const double dT = P.T - (double)aux[(size_t)p * 4 + 3];
     double F[3];
 #pragma unroll
-    for (int c = 0; c < 3; ++c) F[c] = (yv[0] * e1[c] + yv[1] * e2[c] + (DIM == 3 ? yv[2] * e3[c] : 0.0)) * f2;
+    for (int c = 0; c < 3; ++c) F[c] = (yv[0] * e1[c] + yv[1] * e2[c] + (DIM == 3 ? yv[2] * e3[c] : 0.0)) * fs;
     if (DIM == 2) F[2] = 0.0;
-    const double H = yv[3] * M_PI * (DIM == 3 ? D : 1.0) * alpha;
+    const double H = yv[3] * M_PI * (DIM == 3 ? D : 1.0) * alpha * dT;
     MarkerRec<T> rec;
     double r[3], U[3], tt[3];
     marker_setup<DIM, T>(P, make_double4(0.0, 0.0, 0.0, 0.0), r, U, rec, tt);

@@ -105,7 +105,7 @@ def lib():
         L.pibm_mlp_grads.argtypes = [vp, vp, vp, ctypes.c_int, fp, dp]
         L.pibm_mlp_train_step.argtypes = [vp, vp, vp, ctypes.c_int, ctypes.c_float, dp]
         L.pibm_mlp_destroy.argtypes = [vp]
-        L.pibm_features.argtypes = [vp, ctypes.c_int, fp, fp]
+        L.pibm_features.argtypes = [vp, fp, fp]
         L.pibm_set_closure.argtypes = [vp, vp, fp]
         _lib = L
     return _lib
@@ -261,12 +261,12 @@ class Simulation:
         arr = make_particles(P)
         self._check(lib().pibm_set_particles(self._h, arr, len(P)), "pibm_set_particles")
 
-    def features(self, filter: int):
+    def features(self):
         """Closure features (n, 16) and targets (n, 4) of the current state."""
         x = np.empty((self.np, 16), dtype=np.float32)
         t = np.empty((self.np, 4), dtype=np.float32)
         fp = ctypes.POINTER(ctypes.c_float)
-        st = lib().pibm_features(self._h, int(filter), x.ctypes.data_as(fp), t.ctypes.data_as(fp))
+        st = lib().pibm_features(self._h, x.ctypes.data_as(fp), t.ctypes.data_as(fp))
         if st != OK:
             raise PibmError(st, "pibm_features")
         return x, t
