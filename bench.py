@@ -114,6 +114,84 @@ def copy_probe(nbytes=1 << 30, reps=10):
     return dict(bytes_per_launch=2 * nbytes, ms=round(ms, 4), GBs=round(2 * nbytes / (ms * 1e-3) / 1e9, 1))
 
 
+MLP_FLOP_PER_SAMPLE = 2 * (16 * 128 + 128 * 128 + 128 * 128 + 128 * 4)   # forward multiply-adds x 2
+BF16_PEAK_TFLOPS = 2500.0
+
+
+def mlp_variant(steps):
+    """The learned part: inference on 10^6 feature rows and one Adam step on a
+    batch of 4096 through the matrix-core kernels, and a coarse one-point step
+    with the network as the closure (zero weights, so it applies the mean
+    drag and Nusselt factors of its normalisation; the kernels do the same
+    work whatever the weights)."""
+    import numpy as np
+    import torch
+
+    from paper_1502_01159_amd import closure as CL, pibm
+
+    out = {}
+    n = 1 << 20
+    g = torch.Generator(device="cuda").manual_seed(1)
+    x = torch.randn((n, 16), device="cuda", generator=g).to(torch.bfloat16)
+    y = torch.empty((n, 4), device="cuda", dtype=torch.float32)
+    mlp = pibm.Mlp(seed=3, max_batch=4096)
+    mlp.forward(x, y)
+    torch.cuda.synchronize()
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    reps = 20
+    ev0.record()
+    for _ in range(reps):
+        mlp.forward(x, y)
+    ev1.record()
+    torch.cuda.synchronize()
+    ms = ev0.elapsed_time(ev1) / reps
+    tf = MLP_FLOP_PER_SAMPLE * n / (ms * 1e-3) / 1e12
+    out["inference"] = dict(samples=n, ms=round(ms, 4), samples_per_s=round(n / (ms * 1e-3), 0),
+                            TFLOPs=round(tf, 1), frac_bf16_peak=round(tf / BF16_PEAK_TFLOPS, 4))
+    tb = torch.randn((4096, 4), device="cuda", generator=g)
+    xb = x[:4096].contiguous()
+    mlp.train_step(xb, tb, 1e-4)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        mlp.train_step(xb, tb, 1e-4)
+    torch.cuda.synchronize()
+    ms_t = (time.perf_counter() - t0) * 1e3 / reps
+    out["train_step"] = dict(batch=4096, ms=round(ms_t, 4),
+                             TFLOPs=round(3 * MLP_FLOP_PER_SAMPLE * 4096 / (ms_t * 1e-3) / 1e12, 2))
+    # coarse one-point run with the network as the closure
+    cfg, P = CL.fixed_array(L=256, n=4000, D=8.0, seed=41)
+    cc, Pc = CL.coarsen(cfg, P)
+    mlp.set_params(np.zeros(pibm.MLP_NPARAM, dtype=np.float32))
+    norm = np.concatenate([np.zeros(16), np.ones(16), [3.5, 0.0, 0.0, 4.2], np.ones(4)]).astype(np.float32)
+    sim = pibm.Simulation(cc, Pc, storage="f32")
+    sim.set_closure(mlp, norm)
+    sim.step(5)
+    if sim.sync() != pibm.OK:
+        raise RuntimeError("coarse closure run failed in warm-up")
+    sim.profile(True)
+    sim.profile_read()
+    torch.cuda.synchronize()
+    ev0.record()
+    sim.step(steps)
+    ev1.record()
+    torch.cuda.synchronize()
+    ms_c = ev0.elapsed_time(ev1) / steps
+    if sim.sync() != pibm.OK:
+        raise RuntimeError("coarse closure run failed")
+    prof = {k: round(v[0] / max(v[1], 1), 4) for k, v in sim.profile_read().items()}
+    Nc, Nf = sim.N, cfg["nx"] * cfg["ny"] * cfg["nz"]
+    out["coarse_step"] = dict(workload=f"fixed hot spheres, {cc['nx']}^3 coarse lattice (256^3 resolved / 4), "
+                                       f"{len(P)} one-point particles, network closure",
+                              ms_per_step=round(ms_c, 4), coarse_MLUPS=round(Nc / (ms_c * 1e-3) / 1e6, 1),
+                              resolved_equivalent_MLUPS=round(Nf * 16 / (ms_c * 1e-3) / 1e6, 1),
+                              phase_ms_per_step=prof)
+    sim.set_closure(None)
+    sim.close()
+    mlp.close()
+    return out
+
+
 def cpu_baseline(cfg, P, steps):
     from oracle import oracle as O
 
@@ -138,7 +216,8 @@ def main() -> int:
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--workload", default="c3", choices=sorted(WORKLOAD_TEXT))
     ap.add_argument("--storage", default="f32", choices=sorted(STORAGE_BYTES))
-    ap.add_argument("--variants", default="f16,bf16", help="extra storage formats timed beside the main one")
+    ap.add_argument("--variants", default="f16,bf16,mlp",
+                    help="extra storage formats timed beside the main one, and 'mlp' for the learned part")
     ap.add_argument("--cpu-steps", type=int, default=2)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--empty", action="store_true", help="analysis: the same lattice without particles")
@@ -168,7 +247,7 @@ def main() -> int:
     phases = {k: round(v[0] / max(v[1], 1), 4) for k, v in main_run["prof"].items()}
 
     variants = {}
-    for st in [s for s in args.variants.split(",") if s and s != args.storage]:
+    for st in [s for s in args.variants.split(",") if s and s != args.storage and s != "mlp"]:
         r = time_gpu(cfg, P, st, max(args.steps // 2, 10), args.warmup, profile=True)
         lms, ln = r["prof"]["lattice"]
         n_steps = max(args.steps // 2, 10)
@@ -209,6 +288,8 @@ def main() -> int:
         "phase_ms_per_step": phases,
         "variants": variants,
     }
+    if "mlp" in [v for v in args.variants.split(",") if v]:
+        line["mlp"] = mlp_variant(max(args.steps // 2, 10))
     if not args.no_copy_probe:
         line["device_copy"] = copy_probe()
     if not args.no_cpu:
