@@ -455,12 +455,11 @@ int launch_bin(pibm_ctx *c)
     BinArgs b = bin_args(c);
     const int nt = c->P.ntiles;
     hipLaunchKernelGGL(k_fill_int, dim3(std::min(1024, (nt + 255) / 256)), dim3(256), 0, c->stream, b.tile_count, (long long)nt, 0);
-    const int gb = (c->P.np + 127) / 128;
-    hipLaunchKernelGGL((k_bin<false>), dim3(gb), dim3(128), 0, c->stream, b);
+    const int gb = (c->P.np + BIN_THREADS / 64 - 1) / (BIN_THREADS / 64);
+    hipLaunchKernelGGL((k_bin<false>), dim3(gb), dim3(BIN_THREADS), 0, c->stream, b);
     hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, c->stream, (const int *)b.tile_count, b.tile_start, b.tile_fill, nt);
-    hipLaunchKernelGGL((k_bin<true>), dim3(gb), dim3(128), 0, c->stream, b);
-    hipLaunchKernelGGL(k_sort_lists, dim3((nt + 255) / 256), dim3(256), 0, c->stream, (const int *)b.tile_start,
-                       b.tile_items, nt);
+    hipLaunchKernelGGL((k_bin<true>), dim3(gb), dim3(BIN_THREADS), 0, c->stream, b);
+
     return hip_ok(c, hipGetLastError());
 }
 
@@ -516,7 +515,8 @@ int launch_dem(pibm_ctx *c)
     hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, c->stream, (const int *)a.cell_count, a.cell_start, a.cell_fill,
                        c->P.ncells);
     hipLaunchKernelGGL((k_cells<true>), dim3(gb), dim3(128), 0, c->stream, a);
-    hipLaunchKernelGGL(k_neighbours, dim3(gb), dim3(128), 0, c->stream, a);
+    hipLaunchKernelGGL(k_neighbours, dim3((c->P.np + NBR_THREADS / 64 - 1) / (NBR_THREADS / 64)), dim3(NBR_THREADS), 0,
+                       c->stream, a);
     for (int s = 0; s < c->p.n_sub; ++s) {
         a.cur = (const DevParticle *)c->r(c->pcur ? R_PART1 : R_PART0);
         a.nxt = (DevParticle *)c->r(c->pcur ? R_PART0 : R_PART1);

@@ -1317,10 +1317,12 @@ __device__ inline int axis_tiles(double xc, double rext, int n, int per, int T, 
     return cnt;
 }
 
+// One wave per particle; its lanes take the particle's tiles in turn.
+constexpr int BIN_THREADS = 256;
 template <bool FILL>
-__global__ void k_bin(BinArgs a)
+__global__ __launch_bounds__(BIN_THREADS) void k_bin(BinArgs a)
 {
-    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    const int p = blockIdx.x * (BIN_THREADS / 64) + (threadIdx.x >> 6), lane = threadIdx.x & 63;
     if (p >= a.np || halted(a.err)) return;
     const DevParticle P = a.part[p];
     const double re = a.tmpl_rext[P.tmpl];
@@ -1328,7 +1330,7 @@ __global__ void k_bin(BinArgs a)
     bool finite = true;
     for (int d = 0; d < a.dim; ++d) finite = finite && fabs(P.x[d]) < 1.0e8;
     if (!finite) {
-        if (!FILL) atomicOr(a.err, ERR_DOMAIN);
+        if (!FILL && lane == 0) atomicOr(a.err, ERR_DOMAIN);
         return;
     }
     int tx[MAXT_AXIS], ty[MAXT_AXIS], tz[MAXT_AXIS];
@@ -1337,17 +1339,17 @@ __global__ void k_bin(BinArgs a)
     int cz = 1;
     tz[0] = 0;
     if (a.dim == 3) cz = axis_tiles(P.x[2], re, a.nz, a.per[2], a.TZ, tz);
-    for (int k = 0; k < cz; ++k)
-        for (int j = 0; j < cy; ++j)
-            for (int i = 0; i < cx; ++i) {
-                const int t = (tz[k] * a.nty + ty[j]) * a.ntx + tx[i];
-                if (FILL) {
-                    const int pos = atomicAdd(&a.tile_fill[t], 1);
-                    a.tile_items[a.tile_start[t] + pos] = p;
-                } else {
-                    atomicAdd(&a.tile_count[t], 1);
-                }
-            }
+    const int ncomb = cx * cy * cz;
+    for (int c = lane; c < ncomb; c += 64) {
+        const int i = c % cx, j = (c / cx) % cy, k = c / (cx * cy);
+        const int t = (tz[k] * a.nty + ty[j]) * a.ntx + tx[i];
+        if (FILL) {
+            const int pos = atomicAdd(&a.tile_fill[t], 1);
+            a.tile_items[a.tile_start[t] + pos] = p;
+        } else {
+            atomicAdd(&a.tile_count[t], 1);
+        }
+    }
 }
 
 __global__ void k_fill_int(int *p, long long n, int v)
@@ -1365,6 +1367,7 @@ __global__ __launch_bounds__(1024) void k_scan(const int *count, int *start, int
     const int chunk = (n + 1023) / 1024;
     const int b = tid * chunk, e = min(n, b + chunk);
     int s = 0;
+#pragma unroll 16
     for (int i = b; i < e; ++i) s += count[i];
     part[tid] = s;
     __syncthreads();
@@ -1375,6 +1378,7 @@ __global__ __launch_bounds__(1024) void k_scan(const int *count, int *start, int
         __syncthreads();
     }
     int run = tid == 0 ? 0 : part[tid - 1];
+#pragma unroll 16
     for (int i = b; i < e; ++i) {
         start[i] = run;
         run += count[i];
@@ -1383,20 +1387,6 @@ __global__ __launch_bounds__(1024) void k_scan(const int *count, int *start, int
     if (tid == 1023) start[n] = part[1023];
 }
 
-// Each tile's particle list in ascending order (the scatter fills it in
-// arrival order), so that K1 sums its markers in a reproducible order.
-__global__ void k_sort_lists(const int *start, int *items, int n)
-{
-    const int t = blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= n) return;
-    const int b = start[t], e = start[t + 1];
-    for (int i = b + 1; i < e; ++i) {
-        const int v = items[i];
-        int j = i - 1;
-        while (j >= b && items[j] > v) { items[j + 1] = items[j]; --j; }
-        items[j + 1] = v;
-    }
-}
 
 // --------------------------------------------------------------------------
 // K4: DEM cell list and per-particle Verlet list (candidates within
@@ -1479,9 +1469,14 @@ __device__ inline int axis_cells(int c, int nc, int per, int *out)
     return cnt;
 }
 
-__global__ void k_neighbours(DemArgs a)
+// One wave per particle: lane c scans cell c of the 3^d neighbourhood; the
+// hits are gathered and kept in ascending order.
+constexpr int NBR_THREADS = 256;
+__global__ __launch_bounds__(NBR_THREADS) void k_neighbours(DemArgs a)
 {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    __shared__ int hits[NBR_THREADS / 64][MAXN + 64];
+    const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int i = blockIdx.x * (NBR_THREADS / 64) + wv;
     if (i >= a.np || halted(a.err)) return;
     const DevParticle P = a.cur[i];
     const int cx = cell_coord(P.x[0], a.nx, a.per[0], a.ncx, a.cwx);
@@ -1493,34 +1488,50 @@ __global__ void k_neighbours(DemArgs a)
     int nz = 1;
     lz[0] = 0;
     if (a.dim == 3) nz = axis_cells(cz, a.ncz, a.per[2], lz);
-    int list[MAXN];
-    int n = 0;
+    int *h = hits[wv];
+    int n = 0;                                    // wave-uniform
     bool over = false;
-    for (int k = 0; k < nz; ++k)
-        for (int jj = 0; jj < ny; ++jj)
-            for (int ii = 0; ii < nx; ++ii) {
-                const int c = (lz[k] * a.ncy + ly[jj]) * a.ncx + lx[ii];
-                for (int s = a.cell_start[c]; s < a.cell_start[c + 1]; ++s) {
-                    const int j = a.cell_items[s];
-                    if (j == i) continue;
-                    const DevParticle Q = a.cur[j];
-                    double d[3];
-                    min_image(a, P.x, Q.x, d);
-                    const double lim = P.R + Q.R + a.skin;
-                    if (d[0] * d[0] + d[1] * d[1] + d[2] * d[2] < lim * lim) {
-                        if (n < MAXN) {
-                            // insertion keeps ascending order
-                            int pos = n++;
-                            while (pos > 0 && list[pos - 1] > j) { list[pos] = list[pos - 1]; --pos; }
-                            list[pos] = j;
-                        } else over = true;
-                    }
-                }
+    const int ncell = nx * ny * nz;
+    const int cell = lane < ncell ? (lz[lane / (nx * ny)] * a.ncy + ly[(lane / nx) % ny]) * a.ncx + lx[lane % nx] : 0;
+    int s = lane < ncell ? a.cell_start[cell] : 0;
+    const int e = lane < ncell ? a.cell_start[cell + 1] : 0;
+    // one candidate per lane at a time; the lanes advance through their cells together
+    while (__ballot(s < e)) {
+        bool hit = false;
+        int j = -1;
+        if (s < e) {
+            j = a.cell_items[s++];
+            if (j != i) {
+                const DevParticle Q = a.cur[j];
+                double d[3];
+                min_image(a, P.x, Q.x, d);
+                const double lim = P.R + Q.R + a.skin;
+                hit = d[0] * d[0] + d[1] * d[1] + d[2] * d[2] < lim * lim;
             }
-    for (int k = 0; k < n; ++k) a.nbr[(size_t)i * MAXN + k] = list[k];
-    a.nbr_n[i] = n;
-    a.xref[3 * i] = P.x[0]; a.xref[3 * i + 1] = P.x[1]; a.xref[3 * i + 2] = P.x[2];
-    if (over) atomicOr(a.err, ERR_NEIGHBOURS);
+        }
+        const unsigned long long m = __ballot(hit);
+        const int k = (int)__builtin_amdgcn_mbcnt_hi((unsigned)(m >> 32), __builtin_amdgcn_mbcnt_lo((unsigned)m, 0u));
+        if (hit && n + k < MAXN) h[n + k] = j;
+        const int cnt = __popcll(m);
+        if (n + cnt > MAXN) over = true;
+        n = min(n + cnt, MAXN);
+    }
+    __builtin_amdgcn_wave_barrier();
+    if (lane == 0) {
+        for (int q = 1; q < n; ++q) {             // ascending order (insertion)
+            const int v = h[q];
+            int r = q - 1;
+            while (r >= 0 && h[r] > v) { h[r + 1] = h[r]; --r; }
+            h[r + 1] = v;
+        }
+    }
+    __builtin_amdgcn_wave_barrier();
+    for (int q = lane; q < n; q += 64) a.nbr[(size_t)i * MAXN + q] = h[q];
+    if (lane == 0) {
+        a.nbr_n[i] = n;
+        a.xref[3 * i] = P.x[0]; a.xref[3 * i + 1] = P.x[1]; a.xref[3 * i + 2] = P.x[2];
+        if (over) atomicOr(a.err, ERR_NEIGHBOURS);
+    }
 }
 
 // --------------------------------------------------------------------------
