@@ -803,7 +803,9 @@ __device__ __forceinline__ void marker_setup(const DevParticle &P, const double4
 }
 
 constexpr int K2_MAXBOX = 16384;    // cells of a particle's stencil box (bitmap)
-constexpr int K2_MAXSHELL = 2048;   // distinct stencil nodes kept in LDS
+// distinct stencil nodes whose moments are kept in LDS (larger shells gather
+// directly); sized so that several workgroups share a CU
+template <class T> struct K2Shell { static constexpr int MAX = sizeof(T) == 8 ? 1024 : 1280; };
 
 template <int DIM, class SF>
 __global__ __launch_bounds__(256) void k_markers(MkArgs<typename SF::T> a)
@@ -811,11 +813,13 @@ __global__ __launch_bounds__(256) void k_markers(MkArgs<typename SF::T> a)
     using T = typename SF::T;
     using C = typename SF::C;
     using L = Lat<DIM>;
-    __shared__ double red[8][256];
+    constexpr int MAXSHELL = K2Shell<T>::MAX;
+    __shared__ double wred[4][8];
+    __shared__ int spart[256];
     __shared__ uint32_t bits[K2_MAXBOX / 32];
     __shared__ int woff[K2_MAXBOX / 32 + 1];
-    __shared__ int cell[K2_MAXSHELL];
-    __shared__ T mom[DIM + 2][K2_MAXSHELL];       // rho - 1, j, S - T_ref per stencil node
+    __shared__ int cell[MAXSHELL];
+    __shared__ T mom[DIM + 2][MAXSHELL];          // rho - 1, j, S - T_ref per stencil node
     __shared__ int s_total;
     const int p = blockIdx.x, tid = threadIdx.x;
     if (block_halted(a.lb.err)) return;
@@ -855,22 +859,22 @@ __global__ __launch_bounds__(256) void k_markers(MkArgs<typename SF::T> a)
         const int per = (nwords + 255) / 256;
         int local = 0;
         for (int w = tid * per; w < min(nwords, (tid + 1) * per); ++w) local += __popc(bits[w]);
-        red[0][tid] = (double)local;
+        spart[tid] = local;
         __syncthreads();
         for (int off = 1; off < 256; off <<= 1) {
-            const double v = tid >= off ? red[0][tid - off] : 0.0;
+            const int v = tid >= off ? spart[tid - off] : 0;
             __syncthreads();
-            red[0][tid] += v;
+            spart[tid] += v;
             __syncthreads();
         }
-        int run = tid == 0 ? 0 : (int)red[0][tid - 1];
+        int run = tid == 0 ? 0 : spart[tid - 1];
         for (int w = tid * per; w < min(nwords, (tid + 1) * per); ++w) {
             woff[w] = run;
             run += __popc(bits[w]);
         }
-        if (tid == 255) s_total = (int)red[0][255];
+        if (tid == 255) s_total = spart[255];
         __syncthreads();
-        boxed = s_total <= K2_MAXSHELL;            // uniform
+        boxed = s_total <= MAXSHELL;               // uniform
         if (boxed) {
             for (int w = tid; w < nwords; w += 256) {
                 uint32_t b = bits[w];
@@ -967,22 +971,23 @@ __global__ __launch_bounds__(256) void k_markers(MkArgs<typename SF::T> a)
         s[7] += dTl * A;
     }
     if (!a.react) return;
-    __syncthreads();
+    // FP64 sums in a fixed order: butterfly within each wave, then the waves
 #pragma unroll
-    for (int k = 0; k < 8; ++k) red[k][tid] = s[k];
-    __syncthreads();
-    for (int h = 128; h > 0; h >>= 1) {
-        if (tid < h) {
+    for (int off = 32; off; off >>= 1)
 #pragma unroll
-            for (int k = 0; k < 8; ++k) red[k][tid] += red[k][tid + h];
-        }
-        __syncthreads();
-    }
+        for (int k = 0; k < 8; ++k) s[k] += __shfl_xor(s[k], off);
+    if ((tid & 63) == 0)
+#pragma unroll
+        for (int k = 0; k < 8; ++k) wred[tid >> 6][k] = s[k];
+    __syncthreads();
     if (tid == 0) {
+        double t[8];
+#pragma unroll
+        for (int k = 0; k < 8; ++k) t[k] = (wred[0][k] + wred[1][k]) + (wred[2][k] + wred[3][k]);
         DevReact R;
-        R.F[0] = red[0][0]; R.F[1] = red[1][0]; R.F[2] = DIM == 3 ? red[2][0] : 0.0;
-        R.tq[0] = DIM == 3 ? red[3][0] : 0.0; R.tq[1] = DIM == 3 ? red[4][0] : 0.0; R.tq[2] = red[5][0];
-        R.H = red[6][0]; R.dTA = red[7][0];
+        R.F[0] = t[0]; R.F[1] = t[1]; R.F[2] = DIM == 3 ? t[2] : 0.0;
+        R.tq[0] = DIM == 3 ? t[3] : 0.0; R.tq[1] = DIM == 3 ? t[4] : 0.0; R.tq[2] = t[5];
+        R.H = t[6]; R.dTA = t[7];
         a.react[p] = R;
     }
 }
