@@ -29,7 +29,7 @@ size_t up(size_t v) { return (v + ALIGN - 1) / ALIGN * ALIGN; }
 enum Region {
     R_FA, R_GA, R_FB, R_GB, R_PART0, R_PART1, R_REACT, R_TMPL, R_TMPL_START, R_TMPL_REXT, R_MK_START, R_MK,
     R_TCOUNT, R_TSTART, R_TFILL, R_TITEMS, R_CCOUNT, R_CSTART, R_CFILL, R_CITEMS, R_NBR, R_NBRN, R_XREF,
-    R_HID0, R_HXI0, R_HN0, R_HID1, R_HXI1, R_HN1, R_FEAT, R_TARG, R_AUX, R_XBF, R_YMLP, R_NORM, R_ERR, R_COUNT
+    R_HID0, R_HXI0, R_HN0, R_HID1, R_HXI1, R_HN1, R_FEAT, R_TARG, R_AUX, R_XBF, R_YMLP, R_NORM, R_CNTR, R_ERR, R_COUNT
 };
 
 struct Template {
@@ -240,6 +240,7 @@ int make_plan(const pibm_params *p, const pibm_particle *pt, int np, Plan &P)
     sz[R_XBF] = npa * 16 * sizeof(uint16_t);
     sz[R_YMLP] = npa * 4 * sizeof(float);
     sz[R_NORM] = 64 * sizeof(float);
+    sz[R_CNTR] = 64;                               // [0] tile items, [1] cell items
     sz[R_ERR] = 64;
     size_t o = 0;
     for (int r = 0; r < R_COUNT; ++r) { P.off[r] = o; o += up(sz[r]); }
@@ -357,6 +358,7 @@ template <class T> LbmArgs<T> lbm_args(const pibm_ctx *c)
     a.fB = c->r(src ? R_FA : R_FB);
     a.gB = c->r(src ? R_GA : R_GB);
     a.tile_start = (const int *)c->r(R_TSTART);
+    a.tile_count = (const int *)c->r(R_TCOUNT);
     a.tile_items = (const int *)c->r(R_TITEMS);
     a.mk_start = (const int *)c->r(R_MK_START);
     a.mk = (const MarkerRec<T> *)c->r(R_MK);
@@ -454,10 +456,13 @@ int launch_bin(pibm_ctx *c)
     if (c->P.np == 0) return PIBM_OK;
     BinArgs b = bin_args(c);
     const int nt = c->P.ntiles;
-    hipLaunchKernelGGL(k_fill_int, dim3(std::min(1024, (nt + 255) / 256)), dim3(256), 0, c->stream, b.tile_count, (long long)nt, 0);
+    int *cntr = (int *)c->r(R_CNTR);
+    hipLaunchKernelGGL(k_zero2, dim3(std::min(1024, (nt + 256) / 256)), dim3(256), 0, c->stream, b.tile_count, (long long)nt,
+                       cntr, 1LL);
     const int gb = (c->P.np + BIN_THREADS / 64 - 1) / (BIN_THREADS / 64);
     hipLaunchKernelGGL((k_bin<false>), dim3(gb), dim3(BIN_THREADS), 0, c->stream, b);
-    hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, c->stream, (const int *)b.tile_count, b.tile_start, b.tile_fill, nt);
+    hipLaunchKernelGGL(k_alloc, dim3((nt + 255) / 256), dim3(256), 0, c->stream, (const int *)b.tile_count, b.tile_start,
+                       b.tile_fill, nt, cntr);
     hipLaunchKernelGGL((k_bin<true>), dim3(gb), dim3(BIN_THREADS), 0, c->stream, b);
 
     return hip_ok(c, hipGetLastError());
@@ -509,11 +514,12 @@ int launch_dem(pibm_ctx *c)
     DemArgs a = dem_args(c);
     const int gb = (c->P.np + 127) / 128;
     a.cur = (const DevParticle *)c->r(c->pcur ? R_PART1 : R_PART0);
-    hipLaunchKernelGGL(k_fill_int, dim3(std::min(1024, (c->P.ncells + 255) / 256)), dim3(256), 0, c->stream,
-                       a.cell_count, (long long)c->P.ncells, 0);
+    int *cntr = (int *)c->r(R_CNTR) + 1;
+    hipLaunchKernelGGL(k_zero2, dim3(std::min(1024, (c->P.ncells + 256) / 256)), dim3(256), 0, c->stream,
+                       a.cell_count, (long long)c->P.ncells, cntr, 1LL);
     hipLaunchKernelGGL((k_cells<false>), dim3(gb), dim3(128), 0, c->stream, a);
-    hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, c->stream, (const int *)a.cell_count, a.cell_start, a.cell_fill,
-                       c->P.ncells);
+    hipLaunchKernelGGL(k_alloc, dim3((c->P.ncells + 255) / 256), dim3(256), 0, c->stream, (const int *)a.cell_count,
+                       a.cell_start, a.cell_fill, c->P.ncells, cntr);
     hipLaunchKernelGGL((k_cells<true>), dim3(gb), dim3(128), 0, c->stream, a);
     hipLaunchKernelGGL(k_neighbours, dim3((c->P.np + NBR_THREADS / 64 - 1) / (NBR_THREADS / 64)), dim3(NBR_THREADS), 0,
                        c->stream, a);
@@ -753,7 +759,7 @@ int pibm_init(pibm_ctx **out, const pibm_params *p, const pibm_particle *pt, int
     if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
     if (e != hipSuccess) { delete c; return PIBM_EDEVICE; }
     // zeroed small state: tile starts (no particles => empty lists), history counts, error word
-    const int zero_regions[] = {R_TSTART, R_HN0, R_HN1, R_ERR, R_REACT};
+    const int zero_regions[] = {R_TSTART, R_TCOUNT, R_CCOUNT, R_CNTR, R_HN0, R_HN1, R_ERR, R_REACT};
     for (int r : zero_regions) {
         const size_t bytes = c->P.off[r + 1] - c->P.off[r];
         hipLaunchKernelGGL(k_fill_int, dim3(std::max<size_t>(1, std::min<size_t>(1024, (bytes / 4 + 255) / 256))), dim3(256), 0,

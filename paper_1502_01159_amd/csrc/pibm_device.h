@@ -215,7 +215,7 @@ template <typename T> struct LbmArgs {
     double tw[6];                  // T_wall - T_ref per face
     const void *fA, *gA;
     void *fB, *gB;
-    const int *tile_start, *tile_items;
+    const int *tile_start, *tile_count, *tile_items;
     const int *mk_start;
     const MarkerRec<T> *mk;
     int *err;
@@ -458,7 +458,7 @@ __global__ __launch_bounds__(LBM_THREADS) void k_lbm(LbmArgs<typename SF::T> a)
     const int tid = threadIdx.x;
     if (block_halted(a.err)) return;
 
-    const int ps = a.tile_start[t], pe = a.tile_start[t + 1];
+    const int ps = a.tile_start[t], pe = ps + a.tile_count[t];
     const bool has = pe > ps;
     if (has) {
         const int lane = tid & 63, wv = tid >> 6;
@@ -1363,33 +1363,36 @@ __global__ void k_fill_int(int *p, long long n, int v)
         p[i] = v;
 }
 
-// Exclusive scan of count[0..n) into start[0..n], one workgroup of 1024.
-// Also clears fill[0..n) for the scatter pass.
-__global__ __launch_bounds__(1024) void k_scan(const int *count, int *start, int *fill, int n)
+// Disjoint ranges of the items array for the bins: start[i] such that the
+// ranges [start[i], start[i] + count[i]) tile [0, sum count) in some order
+// (a wave prefix sum and one atomic per wave).  Every user of the lists is
+// independent of their order.  Also clears fill[i] for the scatter pass.
+__global__ __launch_bounds__(256) void k_alloc(const int *count, int *start, int *fill, int n, int *total)
 {
-    __shared__ int part[1024];
-    const int tid = threadIdx.x;
-    const int chunk = (n + 1023) / 1024;
-    const int b = tid * chunk, e = min(n, b + chunk);
-    int s = 0;
-#pragma unroll 16
-    for (int i = b; i < e; ++i) s += count[i];
-    part[tid] = s;
-    __syncthreads();
-    for (int off = 1; off < 1024; off <<= 1) {
-        const int v = tid >= off ? part[tid - off] : 0;
-        __syncthreads();
-        part[tid] += v;
-        __syncthreads();
+    const int i = blockIdx.x * blockDim.x + threadIdx.x, lane = threadIdx.x & 63;
+    const int c = i < n ? count[i] : 0;
+    int incl = c;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        const int y = __shfl_up(incl, d);
+        if (lane >= d) incl += y;
     }
-    int run = tid == 0 ? 0 : part[tid - 1];
-#pragma unroll 16
-    for (int i = b; i < e; ++i) {
-        start[i] = run;
-        run += count[i];
-        if (fill) fill[i] = 0;
+    int base = 0;
+    if (lane == 63) base = atomicAdd(total, incl);
+    base = __shfl(base, 63);
+    if (i < n) {
+        start[i] = base + incl - c;
+        fill[i] = 0;
     }
-    if (tid == 1023) start[n] = part[1023];
+}
+
+// Zero two integer arrays in one launch.
+__global__ void k_zero2(int *a, long long na, int *b, long long nb)
+{
+    for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < na + nb; i += (long long)gridDim.x * blockDim.x) {
+        if (i < na) a[i] = 0;
+        else b[i - na] = 0;
+    }
 }
 
 
@@ -1499,7 +1502,7 @@ __global__ __launch_bounds__(NBR_THREADS) void k_neighbours(DemArgs a)
     const int ncell = nx * ny * nz;
     const int cell = lane < ncell ? (lz[lane / (nx * ny)] * a.ncy + ly[(lane / nx) % ny]) * a.ncx + lx[lane % nx] : 0;
     int s = lane < ncell ? a.cell_start[cell] : 0;
-    const int e = lane < ncell ? a.cell_start[cell + 1] : 0;
+    const int e = lane < ncell ? s + a.cell_count[cell] : 0;
     // one candidate per lane at a time; the lanes advance through their cells together
     while (__ballot(s < e)) {
         bool hit = false;
