@@ -421,6 +421,7 @@ __device__ __forceinline__ int wave_prefix5(int cnt, int &total)
     return pre;
 }
 
+
 constexpr int XCD_CHUNK = 8;
 __device__ __forceinline__ int xcd_tile(int b, int G)
 {
@@ -808,7 +809,7 @@ constexpr int K2_MAXBOX = 16384;    // cells of a particle's stencil box (bitmap
 template <class T> struct K2Shell { static constexpr int MAX = sizeof(T) == 8 ? 1024 : 1280; };
 
 template <int DIM, class SF>
-__global__ __launch_bounds__(256) void k_markers(MkArgs<typename SF::T> a)
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k_markers(MkArgs<typename SF::T> a)
 {
     using T = typename SF::T;
     using C = typename SF::C;
@@ -822,9 +823,10 @@ __global__ __launch_bounds__(256) void k_markers(MkArgs<typename SF::T> a)
     __shared__ T mom[DIM + 2][MAXSHELL];          // rho - 1, j, S - T_ref per stencil node
     __shared__ int s_total;
     const int p = blockIdx.x, tid = threadIdx.x;
-    if (block_halted(a.lb.err)) return;
+    // the particle's loads are issued before the halt check's barrier
     const DevParticle P = a.part[p];
     const int m0 = a.mk_start[p], nm = a.mk_start[p + 1] - m0;
+    if (block_halted(a.lb.err)) return;
     const int t0 = a.tmpl_start[P.tmpl];
     const int nn[3] = {a.lb.nx, a.lb.ny, a.lb.nz};
 
@@ -1574,10 +1576,8 @@ __device__ inline void contact(const DemArgs &a, double Ri, const double *n, dou
     Tq[2] = rn[0] * Ft[1] - rn[1] * Ft[0];
 }
 
-__global__ void k_dem(DemArgs a)
+__device__ __forceinline__ void dem_particle(const DemArgs &a, int i)
 {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= a.np) return;
     const DevParticle P = a.cur[i];
     if (halted(a.err)) {
         a.nxt[i] = P;                  // keep both particle copies identical
@@ -1700,6 +1700,14 @@ __global__ void k_dem(DemArgs a)
     if (over) e |= ERR_CONTACTS;
     if (e) atomicOr(a.err, e);
 }
+
+// One sub-step per launch, one thread per particle.
+__global__ void k_dem(DemArgs a)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < a.np) dem_particle(a, i);
+}
+
 
 // Initial state: f = w rho0 and g = w T_init, i.e. deviations 0 and
 // w (T_init - T_ref).
