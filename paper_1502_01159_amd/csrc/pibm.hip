@@ -325,6 +325,7 @@ struct pibm_ctx {
     int cur;        // lattice copy holding the current state (0 = A, 1 = B)
     int pcur;       // particle buffer holding the current state
     int hcur;       // contact-history buffer holding the current state
+    int cells_ok;   // the cell list was built from the current particle state
     long long step;
     int sticky;
     int device_lost;
@@ -396,13 +397,22 @@ int launch_markers(pibm_ctx *c, bool reactions)
     return hip_ok(c, hipGetLastError());
 }
 
+int build_cells(pibm_ctx *c);
+
 template <int DIM, class SF>
 int launch_features(pibm_ctx *c, bool raw, bool for_network)
 {
     using T = typename SF::T;
     if (c->P.np == 0) return PIBM_OK;
+    int st;
+    if ((st = build_cells(c))) return st;
     FeatArgs<T> f{};
     f.lb = lbm_args<T>(c);
+    f.ncx = c->P.ncx; f.ncy = c->P.ncy; f.ncz = c->P.ncz;
+    f.cwx = c->P.cwx; f.cwy = c->P.cwy; f.cwz = c->P.cwz;
+    f.cell_start = (const int *)c->r(R_CSTART);
+    f.cell_count = (const int *)c->r(R_CCOUNT);
+    f.cell_items = (const int *)c->r(R_CITEMS);
     f.part = (const DevParticle *)c->r(c->pcur ? R_PART1 : R_PART0);
     f.np = c->P.np;
     f.nu = c->d.nu;
@@ -508,9 +518,10 @@ DemArgs dem_args(pibm_ctx *c)
     return a;
 }
 
-int launch_dem(pibm_ctx *c)
+// Cell list of the current particle state (kept until the state changes).
+int build_cells(pibm_ctx *c)
 {
-    if (c->P.np == 0) return PIBM_OK;
+    if (c->P.np == 0 || c->cells_ok) return PIBM_OK;
     DemArgs a = dem_args(c);
     const int gb = (c->P.np + 127) / 128;
     a.cur = (const DevParticle *)c->r(c->pcur ? R_PART1 : R_PART0);
@@ -521,6 +532,18 @@ int launch_dem(pibm_ctx *c)
     hipLaunchKernelGGL(k_alloc, dim3((c->P.ncells + 255) / 256), dim3(256), 0, c->stream, (const int *)a.cell_count,
                        a.cell_start, a.cell_fill, c->P.ncells, cntr);
     hipLaunchKernelGGL((k_cells<true>), dim3(gb), dim3(128), 0, c->stream, a);
+    c->cells_ok = 1;
+    return hip_ok(c, hipGetLastError());
+}
+
+int launch_dem(pibm_ctx *c)
+{
+    if (c->P.np == 0) return PIBM_OK;
+    int st;
+    if ((st = build_cells(c))) return st;
+    DemArgs a = dem_args(c);
+    const int gb = (c->P.np + 127) / 128;
+    a.cur = (const DevParticle *)c->r(c->pcur ? R_PART1 : R_PART0);
     hipLaunchKernelGGL(k_neighbours, dim3((c->P.np + NBR_THREADS / 64 - 1) / (NBR_THREADS / 64)), dim3(NBR_THREADS), 0,
                        c->stream, a);
     for (int s = 0; s < c->p.n_sub; ++s) {
@@ -536,6 +559,7 @@ int launch_dem(pibm_ctx *c)
         hipLaunchKernelGGL(k_dem, dim3(gb), dim3(128), 0, c->stream, a);
         c->pcur ^= 1;
         c->hcur ^= 1;
+        c->cells_ok = 0;
     }
     return hip_ok(c, hipGetLastError());
 }
@@ -685,6 +709,7 @@ int upload_particles(pibm_ctx *c, const pibm_particle *pt, int n)
 {
     std::vector<DevParticle> dp(std::max(n, 1));
     for (int i = 0; i < n; ++i) dp[i] = to_dev(pt[i], c->P.ptmpl[i]);
+    c->cells_ok = 0;
     if (n == 0) return PIBM_OK;
     hipError_t e = hipMemcpyAsync(c->r(c->pcur ? R_PART1 : R_PART0), dp.data(), sizeof(DevParticle) * n,
                                   hipMemcpyHostToDevice, c->stream);
@@ -739,7 +764,7 @@ int pibm_init(pibm_ctx **out, const pibm_params *p, const pibm_particle *pt, int
     c->stream = (hipStream_t)stream;
     c->ws = (char *)ws;
     c->ws_bytes = ws_bytes;
-    c->cur = 0; c->pcur = 0; c->hcur = 0; c->step = 0; c->sticky = 0; c->device_lost = 0;
+    c->cur = 0; c->pcur = 0; c->hcur = 0; c->step = 0; c->sticky = 0; c->device_lost = 0; c->cells_ok = 0;
     // templates, marker offsets
     std::vector<double> tm((size_t)std::max(c->P.ntmpl_mk, 1LL) * 4, 0.0);
     std::vector<int> ts(c->P.tmpls.size() + 1, 0);
@@ -986,7 +1011,7 @@ int pibm_load(pibm_ctx *c, const void *buf, size_t n)
         if (e != hipSuccess) return hip_ok(c, e);
         o += b;
     }
-    c->cur = h.cur; c->pcur = h.pcur; c->hcur = h.hcur; c->step = h.step;
+    c->cur = h.cur; c->pcur = h.pcur; c->hcur = h.hcur; c->step = h.step; c->cells_ok = 0;
     return hip_ok(c, hipStreamSynchronize(c->stream));
 }
 

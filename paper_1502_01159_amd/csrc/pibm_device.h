@@ -1023,10 +1023,22 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k
 constexpr int FEAT_THREADS = 256;
 constexpr int FEAT_NB = 4;                      // neighbours kept (3D); 2D keeps 6
 
+// Cell of a centre along one axis (cells of width cw from -1/2).
+__device__ __forceinline__ int cell_coord(double x, int n, int per, int nc, double cw)
+{
+    double y = x + 0.5;
+    if (per) { y = fmod(y, (double)n); if (y < 0) y += n; }
+    int c = (int)floor(y / cw);
+    return c < 0 ? 0 : (c >= nc ? nc - 1 : c);
+}
+
 template <typename T> struct FeatArgs {
     LbmArgs<T> lb;
     const DevParticle *part;
     int np;
+    int ncx, ncy, ncz;             // cell list of the current particle state
+    double cwx, cwy, cwz;          // cell widths (each >= the largest diameter plus the skin)
+    const int *cell_start, *cell_count, *cell_items;
     double nu, alpha, gbeta;
     float *feat;                   // [np][16] raw features (NULL: not stored)
     float *aux;                    // [np][4] slip s and T_f
@@ -1065,8 +1077,8 @@ __global__ __launch_bounds__(FEAT_THREADS) void k_features(FeatArgs<typename SF:
     constexpr int NN = DIM == 3 ? 4 : 6;
     __shared__ double ssum[FEAT_THREADS / 64][6];
     __shared__ double red_phi[FEAT_THREADS / 64];
-    __shared__ double cand_d[FEAT_THREADS * 6];
-    __shared__ int cand_i[FEAT_THREADS * 6];
+    __shared__ double wtop_d[FEAT_THREADS / 64][6], fin_d[6];
+    __shared__ int wtop_i[FEAT_THREADS / 64][6], fin_i[6];
     const int p = blockIdx.x, tid = threadIdx.x;
     if (block_halted(a.lb.err)) return;
     const DevParticle P = a.part[p];
@@ -1122,14 +1134,20 @@ __global__ __launch_bounds__(FEAT_THREADS) void k_features(FeatArgs<typename SF:
         for (int q = 0; q < 5; ++q) ssum[tid >> 6][q] = sm[q];
         ssum[tid >> 6][5] = cnt;
     }
-    // (2) neighbour scan: per-thread nearest NN by (distance, index), solid volume within 2 D
+    // (2) neighbours.  Every centre within 2 D lies in the 5^d cells around
+    // the particle's own (a cell is wider than any diameter), so the solid
+    // volume comes from those cells alone.  Their nearest NN (by distance,
+    // then index) are the nearest of all particles when the NN-th is closer
+    // than two cell widths, the least distance of any centre outside them;
+    // otherwise the nearest are searched again over all particles.
     const double rphi = 2.0 * D;
     double bd[6];
     int bi[6];
+    auto clear = [&]() {
 #pragma unroll
-    for (int q = 0; q < 6; ++q) { bd[q] = 1e300; bi[q] = 0x7fffffff; }
-    double vol = 0.0;
-    for (int jn = tid; jn < a.np; jn += FEAT_THREADS) {
+        for (int q = 0; q < 6; ++q) { bd[q] = 1e300; bi[q] = 0x7fffffff; }
+    };
+    auto offer = [&](int jn, double &vol) {
         const DevParticle Q = a.part[jn];
         double d2 = 0.0;
 #pragma unroll
@@ -1140,9 +1158,8 @@ __global__ __launch_bounds__(FEAT_THREADS) void k_features(FeatArgs<typename SF:
         }
         if (d2 < rphi * rphi)
             vol += DIM == 3 ? (4.0 / 3.0) * M_PI * Q.R * Q.R * Q.R : M_PI * Q.R * Q.R;
-        if (jn == p) continue;
-        // insert into the sorted list (distance, then index)
-        if (d2 < bd[NN - 1] || (d2 == bd[NN - 1] && jn < bi[NN - 1])) {
+        if (jn == p) return;
+        if (d2 < bd[NN - 1] || (d2 == bd[NN - 1] && jn < bi[NN - 1])) {   // sorted insert
             int q = NN - 1;
             while (q > 0 && (d2 < bd[q - 1] || (d2 == bd[q - 1] && jn < bi[q - 1]))) {
                 bd[q] = bd[q - 1]; bi[q] = bi[q - 1];
@@ -1150,31 +1167,102 @@ __global__ __launch_bounds__(FEAT_THREADS) void k_features(FeatArgs<typename SF:
             }
             bd[q] = d2; bi[q] = jn;
         }
+    };
+    // block-wide nearest NN of the threads' sorted lists: NN rounds of a wave
+    // minimum over the list heads, then thread 0 merges the waves' picks
+    auto select = [&]() {
+        for (int r = 0; r < NN; ++r) {
+            double md = bd[0];
+            int mi = bi[0];
+#pragma unroll
+            for (int off = 32; off; off >>= 1) {
+                const double od = __shfl_xor(md, off);
+                const int oi = __shfl_xor(mi, off);
+                if (od < md || (od == md && oi < mi)) { md = od; mi = oi; }
+            }
+            if ((tid & 63) == 0) { wtop_d[tid >> 6][r] = md; wtop_i[tid >> 6][r] = mi; }
+            if (bd[0] == md && bi[0] == mi) {
+#pragma unroll
+                for (int q = 0; q < 5; ++q) { bd[q] = bd[q + 1]; bi[q] = bi[q + 1]; }
+                bd[5] = 1e300; bi[5] = 0x7fffffff;
+            }
+        }
+        __syncthreads();
+        if (tid == 0) {
+            double nd[6];
+            int ni[6];
+#pragma unroll
+            for (int q = 0; q < 6; ++q) { nd[q] = 1e300; ni[q] = 0x7fffffff; }
+            for (int c2 = 0; c2 < (FEAT_THREADS / 64) * NN; ++c2) {
+                const double d2 = wtop_d[c2 / NN][c2 % NN];
+                const int jn = wtop_i[c2 / NN][c2 % NN];
+                if (d2 < nd[NN - 1] || (d2 == nd[NN - 1] && jn < ni[NN - 1])) {
+                    int q = NN - 1;
+                    while (q > 0 && (d2 < nd[q - 1] || (d2 == nd[q - 1] && jn < ni[q - 1]))) {
+                        nd[q] = nd[q - 1]; ni[q] = ni[q - 1];
+                        --q;
+                    }
+                    nd[q] = d2; ni[q] = jn;
+                }
+            }
+            for (int q = 0; q < NN; ++q) { fin_d[q] = nd[q]; fin_i[q] = ni[q]; }
+        }
+        __syncthreads();
+    };
+    constexpr int KR = 2;
+    const int nc[3] = {a.ncx, a.ncy, DIM == 3 ? a.ncz : 1};
+    const double cw[3] = {a.cwx, a.cwy, a.cwz};
+    bool centred = true;
+#pragma unroll
+    for (int d = 0; d < DIM; ++d) centred = centred && isfinite(P.x[d]);
+    int c0[3] = {0, 0, 0}, span[3] = {1, 1, 1};
+    bool full[3] = {true, true, true};
+    double bound = 1e300;                          // least distance of a centre outside the cells scanned
+    if (centred) {
+#pragma unroll
+        for (int d = 0; d < DIM; ++d) {
+            c0[d] = cell_coord(P.x[d], nn[d], a.lb.per[d], nc[d], cw[d]);
+            full[d] = a.lb.per[d] && 2 * KR + 1 >= nc[d];
+            span[d] = full[d] ? nc[d] : 2 * KR + 1;
+            if (!full[d]) bound = fmin(bound, KR * cw[d] * (1.0 - 1e-9));
+        }
+    }
+    double vol = 0.0;
+    clear();
+    const int ncs = centred ? span[0] * span[1] * span[2] : 0;
+    for (int k = tid; k < ncs; k += FEAT_THREADS) {
+        int o[3] = {k % span[0], (k / span[0]) % span[1], k / (span[0] * span[1])};
+        int cell = 0;
+        bool ok = true;
+#pragma unroll
+        for (int d = 2; d >= 0; --d) {
+            int m = o[d];
+            if (!full[d]) {
+                m = c0[d] + o[d] - KR;
+                if (a.lb.per[d]) { m %= nc[d]; if (m < 0) m += nc[d]; }
+                else ok = ok && m >= 0 && m < nc[d];
+            }
+            cell = cell * nc[d] + m;
+        }
+        if (!ok) continue;
+        const int s0 = a.cell_start[cell], e0 = s0 + a.cell_count[cell];
+        for (int it = s0; it < e0; ++it) offer(a.cell_items[it], vol);
     }
 #pragma unroll
     for (int off = 32; off; off >>= 1) vol += __shfl_xor(vol, off);
     if ((tid & 63) == 0) red_phi[tid >> 6] = vol;
-#pragma unroll
-    for (int q = 0; q < NN; ++q) { cand_d[tid * NN + q] = bd[q]; cand_i[tid * NN + q] = bi[q]; }
-    __syncthreads();
-    if (tid != 0) return;
-    // merge the candidates (thread 0, fixed order)
-    double nd[6];
-    int ni[6];
-#pragma unroll
-    for (int q = 0; q < 6; ++q) { nd[q] = 1e300; ni[q] = 0x7fffffff; }
-    for (int c2 = 0; c2 < FEAT_THREADS * NN; ++c2) {
-        const double d2 = cand_d[c2];
-        const int jn = cand_i[c2];
-        if (d2 < nd[NN - 1] || (d2 == nd[NN - 1] && jn < ni[NN - 1])) {
-            int q = NN - 1;
-            while (q > 0 && (d2 < nd[q - 1] || (d2 == nd[q - 1] && jn < ni[q - 1]))) {
-                nd[q] = nd[q - 1]; ni[q] = ni[q - 1];
-                --q;
-            }
-            nd[q] = d2; ni[q] = jn;
-        }
+    select();
+    const bool all_scanned = centred && full[0] && full[1] && full[2];
+    const bool exact = all_scanned || (fin_i[NN - 1] != 0x7fffffff && fin_d[NN - 1] < bound * bound);
+    if (!exact) {
+        double dummy = 0.0;
+        clear();
+        for (int jn = tid; jn < a.np; jn += FEAT_THREADS) offer(jn, dummy);
+        select();
     }
+    if (tid != 0) return;
+    int ni[6];
+    for (int q = 0; q < NN; ++q) ni[q] = fin_i[q];
     double vtot = 0.0;
     for (int w = 0; w < FEAT_THREADS / 64; ++w) vtot += red_phi[w];
     // (3) fluid seen by the particle (waves summed in a fixed order)
@@ -1424,14 +1512,6 @@ struct DemArgs {
     int last;                      // last sub-step: apply the thermosensitive update
     int *err;
 };
-
-__device__ __forceinline__ int cell_coord(double x, int n, int per, int nc, double cw)
-{
-    double y = x + 0.5;
-    if (per) { y = fmod(y, (double)n); if (y < 0) y += n; }
-    int c = (int)floor(y / cw);
-    return c < 0 ? 0 : (c >= nc ? nc - 1 : c);
-}
 
 template <bool FILL>
 __global__ void k_cells(DemArgs a)

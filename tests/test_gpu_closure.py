@@ -47,16 +47,46 @@ def reference(oracle_mod, ref, cfg):
     return X, T, s, d, Tf
 
 
-@pytest.mark.parametrize("name,mode", [("c3_small", 1), ("c2_small", 1), ("c3_small", 2)])
+def coarse_array():
+    """150 fixed spheres of D = 8 in a periodic 96^3 box, coarsened 4x: points
+    of D = 2 on a 24^3 lattice, cells of width 3 (8 per axis), so the
+    neighbour search covers part of the box: the 4 nearest of most particles
+    lie within two cell widths, those of the rest do not."""
+    from paper_1502_01159_amd import closure as CL
+
+    cfg, P = CL.fixed_array(L=96, n=150, D=8.0, seed=21)
+    return CL.coarsen(cfg, P, c=4)
+
+
+def nearest_within_cells(P, cfg, nn=4, width=3.0):
+    """Per particle: whether its nn-th nearest centre (minimum image) lies
+    within two cell widths."""
+    L = np.array([cfg["nx"], cfg["ny"], cfg["nz"]], dtype=float)
+    x = P[:, 0:3]
+    d = x[None, :, :] - x[:, None, :]
+    d -= L * np.rint(d / L)
+    r = np.sqrt((d * d).sum(-1))
+    np.fill_diagonal(r, np.inf)
+    return np.sort(r, axis=1)[:, nn - 1] < 2 * width
+
+
+@pytest.mark.parametrize("name,mode", [("c3_small", 1), ("c2_small", 1), ("c3_small", 2), ("coarse_array", 2)])
 def test_features_and_targets_match_oracle(gpu, oracle_mod, name, mode):
-    cfg, P = W.workload(name)
+    if name == "coarse_array":
+        cfg, P = coarse_array()
+        inside = nearest_within_cells(P, cfg)
+        assert inside.any() and not inside.all()   # both branches of the search are taken
+        steps = 8
+    else:
+        cfg, P = W.workload(name)
+        steps = 40
     cfg = W.with_overrides(cfg, marker_mode=mode)
-    if mode == 2:
+    if mode == 2 and name != "coarse_array":
         P = sub_grid(P)
     sim = gpu.Simulation(cfg, P, storage="f64")
     ref = oracle_mod.Oracle(cfg, P)
-    sim.step(40)
-    ref.step(40)
+    sim.step(steps)
+    ref.step(steps)
     x, t = sim.features()
     X, T, _, _, _ = reference(oracle_mod, ref, cfg)
     # FP64 on both sides, FP32 on output
