@@ -95,6 +95,9 @@ __device__ __forceinline__ uint32_t sr_bits(uint32_t seed, int k)
 // population are so kept on average instead of being discarded every step;
 // the hash makes it reproducible bit for bit.  `w` is the lattice weight of
 // the direction (16-bit formats store dev / w).
+// The lattice update's stores are non-temporal: the next copy is read only
+// in the next step, and keeping it out of L2 leaves room there for the
+// neighbouring tiles' rows that this step's gathers read again.
 // --------------------------------------------------------------------------
 struct StF32 {
     using S = float; using T = float; using C = double;
@@ -105,14 +108,17 @@ struct StF32 {
         // double -> float keeps 24 of 53 mantissa bits: randomise the 29 cut
         unsigned long long b = (unsigned long long)__double_as_longlong((double)old + inc);
         b = (b + ((unsigned long long)r16 << 13)) & ~0x1fffffffull;
-        *p = (float)__longlong_as_double((long long)b);
+        __builtin_nontemporal_store((float)__longlong_as_double((long long)b), p);
     }
 };
 struct StF64 {
     using S = double; using T = double; using C = double;
     static __device__ __forceinline__ T cvt(S v, double) { return v; }
     static __device__ __forceinline__ void st(S *p, T v, double) { *p = v; }
-    static __device__ __forceinline__ void st_sum(S *p, T old, C inc, double, uint32_t) { *p = old + inc; }
+    static __device__ __forceinline__ void st_sum(S *p, T old, C inc, double, uint32_t)
+    {
+        __builtin_nontemporal_store(old + inc, p);
+    }
 };
 struct StF16 {
     using S = __half; using T = float; using C = float;
@@ -125,7 +131,7 @@ struct StF16 {
         // 2^-14 it rounds to nearest)
         const float s = (old + inc) * (float)(1.0 / w);
         const uint32_t b = (__float_as_uint(s) + (r16 >> 3)) & ~0x1fffu;
-        *p = __float2half_rn(__uint_as_float(b));
+        __builtin_nontemporal_store(__half_as_ushort(__float2half_rn(__uint_as_float(b))), (unsigned short *)p);
     }
 };
 struct StBF16 {
@@ -144,7 +150,7 @@ struct StBF16 {
         const uint32_t u = __float_as_uint(s);
         // NaN keeps a non-zero mantissa; otherwise randomise the 16 cut bits
         const uint32_t r = (u & 0x7fffffffu) > 0x7f800000u ? (u | 0x00400000u) : u + r16;
-        *p = (uint16_t)(r >> 16);
+        __builtin_nontemporal_store((uint16_t)(r >> 16), p);
     }
 };
 
@@ -1396,18 +1402,33 @@ struct BinArgs {
 
 constexpr int MAXT_AXIS = 32;
 
+// Tiles along one axis that hold a node of floor(xc - rext) - 1 ..
+// floor(xc + rext) + 2 (wrapped on a periodic axis, clipped otherwise), in
+// the order the nodes first reach them; at most MAXT_AXIS.
 __device__ inline int axis_tiles(double xc, double rext, int n, int per, int T, int *out)
 {
     const int lo = (int)floor(xc - rext) - 1, hi = (int)floor(xc + rext) + 2;
     int cnt = 0;
-    for (int c = lo; c <= hi; ++c) {
-        int m = c;
-        if (per) { m %= n; if (m < 0) m += n; }
-        else if (m < 0 || m >= n) continue;
-        const int t = m / T;
-        bool dup = false;
-        for (int k = 0; k < cnt; ++k) dup = dup || out[k] == t;
-        if (!dup && cnt < MAXT_AXIS) out[cnt++] = t;
+    auto run = [&](int a, int b) {                 // the tiles of nodes a..b (0 <= a <= b < n)
+        for (int t = a / T; t <= b / T; ++t) {
+            bool dup = false;
+            for (int k = 0; k < cnt; ++k) dup = dup || out[k] == t;
+            if (!dup && cnt < MAXT_AXIS) out[cnt++] = t;
+        }
+    };
+    if (!per) {
+        if (max(lo, 0) <= min(hi, n - 1)) run(max(lo, 0), min(hi, n - 1));
+    } else if (hi - lo + 1 >= n) {
+        int m = lo % n;
+        if (m < 0) m += n;
+        run(m, n - 1);
+        if (m > 0) run(0, m - 1);
+    } else {
+        int m = lo % n;
+        if (m < 0) m += n;
+        const int e = m + (hi - lo);
+        if (e < n) run(m, e);
+        else { run(m, n - 1); run(0, e - n); }
     }
     return cnt;
 }
