@@ -28,6 +28,7 @@ size_t up(size_t v) { return (v + ALIGN - 1) / ALIGN * ALIGN; }
 
 enum Region {
     R_FA, R_GA, R_FB, R_GB, R_PART0, R_PART1, R_REACT, R_TMPL, R_TMPL_START, R_TMPL_REXT, R_MK_START, R_MK,
+    R_TP_START, R_TP_BOX, R_GP_START, R_GP_BASE,
     R_TCOUNT, R_TSTART, R_TFILL, R_TITEMS, R_CCOUNT, R_CSTART, R_CFILL, R_CITEMS, R_NBR, R_NBRN, R_XREF,
     R_HID0, R_HXI0, R_HN0, R_HID1, R_HXI1, R_HN1, R_FEAT, R_TARG, R_AUX, R_XBF, R_YMLP, R_NORM, R_CNTR, R_ERR, R_COUNT
 };
@@ -35,6 +36,8 @@ enum Region {
 struct Template {
     double R;
     std::vector<double> off;       // 4 per marker: r_x, r_y, r_z, A
+    std::vector<int> pbeg;         // patches: first marker of each (one more entry: the count)
+    std::vector<double> pbox;      // 6 per patch: least r_x, r_y, r_z, then greatest
 };
 
 struct Plan {
@@ -49,6 +52,10 @@ struct Plan {
     std::vector<Template> tmpls;
     std::vector<int> ptmpl;        // template of each particle
     std::vector<int> mk_start;     // np + 1
+    std::vector<int> tp_start;     // ntmpl + 1: first patch of each template
+    std::vector<double> tp_box;    // 6 per template patch
+    std::vector<int> gp_start;     // ngp + 1: first marker of each particle patch
+    std::vector<int> gp_base;      // np + 1: first particle patch of each particle
     long long nmk, ntmpl_mk;
     long long tile_cap;
     size_t off[R_COUNT + 1];
@@ -84,6 +91,39 @@ Derived derive(const pibm_params &p)
 // Lagrangian points on the body surface: a ring of round(pi D / s) points
 // (2D) or a Fibonacci sphere of round(pi D^2 / s^2) points (3D); weights per
 // pibm_markers.
+// Patches of a template: its points grouped by the cell of their (y, z)
+// offset, cells of one tile's extent (py x pz), each with the box of its
+// offsets.  The points are reordered patch by patch.
+void make_patches(Template &t, int dim, int py, int pz)
+{
+    const int n = (int)(t.off.size() / 4);
+    std::vector<std::pair<long long, int>> key(n);
+    for (int k = 0; k < n; ++k) {
+        const long long ky = (long long)std::floor((t.off[4 * k + 1] + t.R) / py);
+        const long long kz = dim == 3 ? (long long)std::floor((t.off[4 * k + 2] + t.R) / pz) : 0;
+        key[k] = {kz * (1LL << 20) + ky, k};
+    }
+    std::sort(key.begin(), key.end());
+    std::vector<double> off(t.off.size());
+    t.pbeg.clear();
+    t.pbox.clear();
+    for (int k = 0; k < n; ++k) {
+        std::copy(t.off.begin() + 4 * key[k].second, t.off.begin() + 4 * key[k].second + 4, off.begin() + 4 * k);
+        if (k == 0 || key[k].first != key[k - 1].first) {
+            t.pbeg.push_back(k);
+            t.pbox.insert(t.pbox.end(), {1e300, 1e300, 1e300, -1e300, -1e300, -1e300});
+        }
+        double *b = &t.pbox[t.pbox.size() - 6];
+        for (int d = 0; d < 3; ++d) {
+            const double r = d < dim ? off[4 * k + d] : 0.0;
+            b[d] = std::min(b[d], r);
+            b[3 + d] = std::max(b[3 + d], r);
+        }
+    }
+    t.pbeg.push_back(n);
+    t.off.swap(off);
+}
+
 Template make_template(int dim, double R, int mode, double s)
 {
     const double pi = 3.14159265358979323846;
@@ -113,12 +153,6 @@ Template make_template(int dim, double R, int mode, double s)
         }
     }
     return t;
-}
-
-int tiles_along(double rext, int n, int T)
-{
-    const int span = (int)std::ceil(2.0 * rext) + 5;
-    return std::min((n + T - 1) / T, (span - 1) / T + 2);
 }
 
 int check_params(const pibm_params *p)
@@ -174,6 +208,7 @@ int make_plan(const pibm_params *p, const pibm_particle *pt, int np, Plan &P)
             if (P.tmpls[t].R == R) { k = (int)t; break; }
         if (k < 0) {
             P.tmpls.push_back(make_template(p->dim, R, p->marker_mode, s));
+            make_patches(P.tmpls.back(), p->dim, P.TY, P.TZ);
             k = (int)P.tmpls.size() - 1;
         }
         P.ptmpl[i] = k;
@@ -190,14 +225,42 @@ int make_plan(const pibm_params *p, const pibm_particle *pt, int np, Plan &P)
         P.mk_start[i + 1] = (int)nmk;
     }
     P.nmk = nmk;
-    // tile-list capacity: every tile a particle's footprint can touch
+    // patches of templates and particles
+    P.tp_start.assign(P.tmpls.size() + 1, 0);
+    P.tp_box.clear();
+    for (size_t t = 0; t < P.tmpls.size(); ++t) {
+        P.tp_start[t + 1] = P.tp_start[t] + (int)P.tmpls[t].pbeg.size() - 1;
+        P.tp_box.insert(P.tp_box.end(), P.tmpls[t].pbox.begin(), P.tmpls[t].pbox.end());
+    }
+    P.gp_base.assign(np + 1, 0);
+    P.gp_start.clear();
+    for (int i = 0; i < np; ++i) {
+        const Template &t = P.tmpls[P.ptmpl[i]];
+        const long long ng = (long long)P.gp_base[i] + (long long)t.pbeg.size() - 1;
+        if (ng >= (1LL << 30)) return PIBM_EINVAL;
+        P.gp_base[i + 1] = (int)ng;
+        for (size_t k = 0; k + 1 < t.pbeg.size(); ++k) P.gp_start.push_back(P.mk_start[i] + t.pbeg[k]);
+    }
+    P.gp_start.push_back((int)P.nmk);
+    // tile-list capacity: every tile a patch's footprint can reach.  The
+    // footprint spans at most ceil(extent) + 4 nodes per axis; a wrapped span
+    // on a periodic axis whose last tile is short can touch one tile more.
+    const int nn[3] = {p->nx, p->ny, p->nz}, TT[3] = {P.TX, P.TY, P.TZ};
     P.tile_cap = 0;
     for (int i = 0; i < np; ++i) {
         const double re = p->marker_mode == PIBM_MARKERS_POINT ? 0.0 : pt[i].R;
         if ((int)std::ceil(2.0 * re) + 5 > (MAXT_AXIS - 1) * P.TY) return PIBM_EINVAL;
-        long long c = (long long)tiles_along(re, p->nx, P.TX) * tiles_along(re, p->ny, P.TY);
-        if (p->dim == 3) c *= tiles_along(re, p->nz, P.TZ);
-        P.tile_cap += c;
+        const Template &t = P.tmpls[P.ptmpl[i]];
+        for (size_t k = 0; k + 1 < t.pbeg.size(); ++k) {
+            long long c = 1;
+            for (int d = 0; d < p->dim; ++d) {
+                const int span = (int)std::ceil(t.pbox[6 * k + 3 + d] - t.pbox[6 * k + d] + 1e-9) + 4;
+                const int ntd = (nn[d] + TT[d] - 1) / TT[d];
+                const int extra = p->periodic[d] && nn[d] % TT[d] != 0 ? 1 : 0;
+                c *= std::min(ntd, (span - 1) / TT[d] + 2 + extra);
+            }
+            P.tile_cap += c;
+        }
     }
     // DEM cells of width >= 2 Rmax + skin
     const double cs = std::max(2.0 * Rmax + P.skin, 1.0);
@@ -219,6 +282,10 @@ int make_plan(const pibm_params *p, const pibm_particle *pt, int np, Plan &P)
     sz[R_TMPL_START] = (P.tmpls.size() + 1) * sizeof(int);
     sz[R_TMPL_REXT] = (P.tmpls.size() + 1) * sizeof(double);
     sz[R_MK_START] = (npa + 1) * sizeof(int);
+    sz[R_TP_START] = P.tp_start.size() * sizeof(int);
+    sz[R_TP_BOX] = std::max<size_t>(P.tp_box.size(), 6) * sizeof(double);
+    sz[R_GP_START] = P.gp_start.size() * sizeof(int);
+    sz[R_GP_BASE] = P.gp_base.size() * sizeof(int);
     sz[R_MK] = std::max(P.nmk, 1LL) * (p->storage == PIBM_STORE_F64 ? sizeof(MarkerRec<double>) : sizeof(MarkerRec<float>));
     sz[R_TCOUNT] = (size_t)P.ntiles * sizeof(int);
     sz[R_TSTART] = (size_t)(P.ntiles + 1) * sizeof(int);
@@ -361,7 +428,7 @@ template <class T> LbmArgs<T> lbm_args(const pibm_ctx *c)
     a.tile_start = (const int *)c->r(R_TSTART);
     a.tile_count = (const int *)c->r(R_TCOUNT);
     a.tile_items = (const int *)c->r(R_TITEMS);
-    a.mk_start = (const int *)c->r(R_MK_START);
+    a.gp_start = (const int *)c->r(R_GP_START);
     a.mk = (const MarkerRec<T> *)c->r(R_MK);
     a.err = (int *)c->r(R_ERR);
     a.macro = nullptr;
@@ -452,7 +519,10 @@ BinArgs bin_args(pibm_ctx *c)
     b.ntx = c->P.ntx; b.nty = c->P.nty; b.ntz = c->P.ntz;
     b.np = c->P.np;
     b.part = (const DevParticle *)c->r(c->pcur ? R_PART1 : R_PART0);
-    b.tmpl_rext = (const double *)c->r(R_TMPL_REXT);
+    b.tp_start = (const int *)c->r(R_TP_START);
+    b.tp_box = (const double *)c->r(R_TP_BOX);
+    b.gp_base = (const int *)c->r(R_GP_BASE);
+    b.cap = c->P.tile_cap;
     b.tile_count = (int *)c->r(R_TCOUNT);
     b.tile_start = (int *)c->r(R_TSTART);
     b.tile_fill = (int *)c->r(R_TFILL);
@@ -719,7 +789,7 @@ int upload_particles(pibm_ctx *c, const pibm_particle *pt, int n)
 
 int status_from_err(int e)
 {
-    if (e & (ERR_CONTACTS | ERR_NEIGHBOURS)) return PIBM_ENOMEM;
+    if (e & (ERR_CONTACTS | ERR_NEIGHBOURS | ERR_TILES)) return PIBM_ENOMEM;
     if (e) return PIBM_EUNSTABLE;
     return PIBM_OK;
 }
@@ -781,6 +851,11 @@ int pibm_init(pibm_ctx **out, const pibm_params *p, const pibm_particle *pt, int
     if (e == hipSuccess) e = hipMemcpyAsync(c->r(R_TMPL_START), ts.data(), ts.size() * sizeof(int), hipMemcpyHostToDevice, c->stream);
     if (e == hipSuccess) e = hipMemcpyAsync(c->r(R_TMPL_REXT), rext.data(), rext.size() * sizeof(double), hipMemcpyHostToDevice, c->stream);
     if (e == hipSuccess) e = hipMemcpyAsync(c->r(R_MK_START), c->P.mk_start.data(), c->P.mk_start.size() * sizeof(int), hipMemcpyHostToDevice, c->stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(c->r(R_TP_START), c->P.tp_start.data(), c->P.tp_start.size() * sizeof(int), hipMemcpyHostToDevice, c->stream);
+    if (e == hipSuccess && !c->P.tp_box.empty())
+        e = hipMemcpyAsync(c->r(R_TP_BOX), c->P.tp_box.data(), c->P.tp_box.size() * sizeof(double), hipMemcpyHostToDevice, c->stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(c->r(R_GP_START), c->P.gp_start.data(), c->P.gp_start.size() * sizeof(int), hipMemcpyHostToDevice, c->stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(c->r(R_GP_BASE), c->P.gp_base.data(), c->P.gp_base.size() * sizeof(int), hipMemcpyHostToDevice, c->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
     if (e != hipSuccess) { delete c; return PIBM_EDEVICE; }
     // zeroed small state: tile starts (no particles => empty lists), history counts, error word

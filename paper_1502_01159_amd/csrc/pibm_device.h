@@ -180,6 +180,7 @@ enum : int {
     ERR_NEIGHBOURS = 4,   // neighbour list full
     ERR_STALE = 8,        // a particle moved more than skin/2 since the list was built
     ERR_DOMAIN = 16,      // particle centre outside the walls / NaN state
+    ERR_TILES = 32,       // tile lists full
 };
 
 // Once the watchdog word is set the state is no longer meaningful; every
@@ -221,8 +222,8 @@ template <typename T> struct LbmArgs {
     double tw[6];                  // T_wall - T_ref per face
     const void *fA, *gA;
     void *fB, *gB;
-    const int *tile_start, *tile_count, *tile_items;
-    const int *mk_start;
+    const int *tile_start, *tile_count, *tile_items;   // items: particle patch ids
+    const int *gp_start;           // first point of each particle patch (one more entry: the total)
     const MarkerRec<T> *mk;
     int *err;
     T *macro;                      // macro pass: rho, u[3], T at k * Ns + n
@@ -469,13 +470,13 @@ __global__ __launch_bounds__(LBM_THREADS) void k_lbm(LbmArgs<typename SF::T> a)
     const bool has = pe > ps;
     if (has) {
         const int lane = tid & 63, wv = tid >> 6;
-        // the first 64 entries of the tile's particle list, loaded while the
-        // accumulators are cleared
+        // the first 64 entries of the tile's list of particle patches, loaded
+        // while the accumulators are cleared
         int pm0 = 0, pn = 0;
         if (lane < pe - ps) {
-            const int p = a.tile_items[ps + lane];
-            pm0 = a.mk_start[p];
-            pn = a.mk_start[p + 1] - pm0;
+            const int g = a.tile_items[ps + lane];
+            pm0 = a.gp_start[g];
+            pn = a.gp_start[g + 1] - pm0;
         }
         for (int i = tid; i < NC * NROW * PXU; i += LBM_THREADS) (&acc[0][0])[i] = 0ull;
         __syncthreads();
@@ -567,8 +568,8 @@ __global__ __launch_bounds__(LBM_THREADS) void k_lbm(LbmArgs<typename SF::T> a)
             }
         };
 
-        // The list in batches of 64 particles; within a batch the points of
-        // all its particles form one virtual array, cut into chunks of 64
+        // The list in batches of 64 patches; within a batch the points of
+        // all its patches form one virtual array, cut into chunks of 64
         // that the waves take in turn (chunk0 carries the turn across
         // batches), KSCAN chunks per wave at a time.
         int chunk0 = 0;
@@ -577,9 +578,9 @@ __global__ __launch_bounds__(LBM_THREADS) void k_lbm(LbmArgs<typename SF::T> a)
             if (e0 != ps) {
                 pm0 = 0; pn = 0;
                 if (lane < ne) {
-                    const int p = a.tile_items[e0 + lane];
-                    pm0 = a.mk_start[p];
-                    pn = a.mk_start[p + 1] - pm0;
+                    const int g = a.tile_items[e0 + lane];
+                    pm0 = a.gp_start[g];
+                    pn = a.gp_start[g + 1] - pm0;
                 }
             }
             int incl = pn;                            // inclusive prefix over the batch
@@ -598,7 +599,7 @@ __global__ __launch_bounds__(LBM_THREADS) void k_lbm(LbmArgs<typename SF::T> a)
                 for (int i = 0; i < KSCAN; ++i) {
                     const int v = 64 * (c + 4 * i) + lane;
                     const int vs = min(v, tot_m - 1);
-                    // particle holding virtual index vs: the last e < ne with pre[e] <= vs
+                    // patch holding virtual index vs: the last e < ne with pre[e] <= vs
                     int e = 0;
 #pragma unroll
                     for (int st = 32; st; st >>= 1) {
@@ -1395,45 +1396,49 @@ struct BinArgs {
     int TX, TY, TZ, ntx, nty, ntz;
     int np;
     const DevParticle *part;
-    const double *tmpl_rext;
+    const int *tp_start;           // ntmpl + 1: first patch of each template
+    const double *tp_box;          // 6 per patch: least and greatest offset per axis
+    const int *gp_base;            // np + 1: first patch id of each particle
+    long long cap;                 // capacity of tile_items
     int *tile_count, *tile_start, *tile_fill, *tile_items;
     int *err;
 };
 
-constexpr int MAXT_AXIS = 32;
+constexpr int MAXT_AXIS = 32;     // particles whose footprint spans more tiles per axis are refused
 
-// Tiles along one axis that hold a node of floor(xc - rext) - 1 ..
-// floor(xc + rext) + 2 (wrapped on a periodic axis, clipped otherwise), in
-// the order the nodes first reach them; at most MAXT_AXIS.
-__device__ inline int axis_tiles(double xc, double rext, int n, int per, int T, int *out)
+// Tiles along one axis that hold a node of lo .. hi (wrapped on a periodic
+// axis, clipped otherwise): first .. first + cntA - 1, then 0 .. cnt - cntA
+// - 1 (the part of a wrapped range that lies below `first`), each once.
+struct AxisRun { int first, cntA, cnt; };
+__device__ inline AxisRun axis_run(int lo, int hi, int n, int per, int T)
 {
-    const int lo = (int)floor(xc - rext) - 1, hi = (int)floor(xc + rext) + 2;
-    int cnt = 0;
-    auto run = [&](int a, int b) {                 // the tiles of nodes a..b (0 <= a <= b < n)
-        for (int t = a / T; t <= b / T; ++t) {
-            bool dup = false;
-            for (int k = 0; k < cnt; ++k) dup = dup || out[k] == t;
-            if (!dup && cnt < MAXT_AXIS) out[cnt++] = t;
-        }
-    };
+    AxisRun r{0, 0, 0};
     if (!per) {
-        if (max(lo, 0) <= min(hi, n - 1)) run(max(lo, 0), min(hi, n - 1));
-    } else if (hi - lo + 1 >= n) {
-        int m = lo % n;
-        if (m < 0) m += n;
-        run(m, n - 1);
-        if (m > 0) run(0, m - 1);
-    } else {
-        int m = lo % n;
-        if (m < 0) m += n;
-        const int e = m + (hi - lo);
-        if (e < n) run(m, e);
-        else { run(m, n - 1); run(0, e - n); }
+        const int a = max(lo, 0), b = min(hi, n - 1);
+        if (a <= b) { r.first = a / T; r.cntA = r.cnt = b / T - a / T + 1; }
+        return r;
     }
-    return cnt;
+    int m = lo % n;
+    if (m < 0) m += n;
+    r.first = m / T;
+    if (hi - lo + 1 >= n) {                        // every node
+        r.cntA = (n - 1) / T - r.first + 1;
+        r.cnt = r.cntA + r.first;
+        return r;
+    }
+    const int e = m + (hi - lo);
+    if (e < n) { r.cntA = r.cnt = e / T - r.first + 1; return r; }
+    r.cntA = (n - 1) / T - r.first + 1;
+    r.cnt = r.cntA + min((e - n) / T, r.first - 1) + 1;
+    return r;
 }
+__device__ __forceinline__ int axis_tile(const AxisRun &r, int i) { return i < r.cntA ? r.first + i : i - r.cntA; }
 
-// One wave per particle; its lanes take the particle's tiles in turn.
+// One wave per particle.  Its points are grouped in patches (boxes of
+// offsets from the centre); the tiles of a patch are those its points'
+// footprints (nodes floor(X) - 1 .. floor(X) + 2 per axis) can reach.  The
+// lanes take the particle's (patch, tile) pairs in turn; an item names the
+// particle's patch, so the lattice kernel scans only the points near a tile.
 constexpr int BIN_THREADS = 256;
 template <bool FILL>
 __global__ __launch_bounds__(BIN_THREADS) void k_bin(BinArgs a)
@@ -1441,7 +1446,6 @@ __global__ __launch_bounds__(BIN_THREADS) void k_bin(BinArgs a)
     const int p = blockIdx.x * (BIN_THREADS / 64) + (threadIdx.x >> 6), lane = threadIdx.x & 63;
     if (p >= a.np || halted(a.err)) return;
     const DevParticle P = a.part[p];
-    const double re = a.tmpl_rext[P.tmpl];
     // a non-finite or runaway centre would give meaningless loop bounds
     bool finite = true;
     for (int d = 0; d < a.dim; ++d) finite = finite && fabs(P.x[d]) < 1.0e8;
@@ -1449,21 +1453,59 @@ __global__ __launch_bounds__(BIN_THREADS) void k_bin(BinArgs a)
         if (!FILL && lane == 0) atomicOr(a.err, ERR_DOMAIN);
         return;
     }
-    int tx[MAXT_AXIS], ty[MAXT_AXIS], tz[MAXT_AXIS];
-    const int cx = axis_tiles(P.x[0], re, a.nx, a.per[0], a.TX, tx);
-    const int cy = axis_tiles(P.x[1], re, a.ny, a.per[1], a.TY, ty);
-    int cz = 1;
-    tz[0] = 0;
-    if (a.dim == 3) cz = axis_tiles(P.x[2], re, a.nz, a.per[2], a.TZ, tz);
-    const int ncomb = cx * cy * cz;
-    for (int c = lane; c < ncomb; c += 64) {
-        const int i = c % cx, j = (c / cx) % cy, k = c / (cx * cy);
-        const int t = (tz[k] * a.nty + ty[j]) * a.ntx + tx[i];
-        if (FILL) {
-            const int pos = atomicAdd(&a.tile_fill[t], 1);
-            a.tile_items[a.tile_start[t] + pos] = p;
-        } else {
-            atomicAdd(&a.tile_count[t], 1);
+    const int k0 = a.tp_start[P.tmpl], nk = a.tp_start[P.tmpl + 1] - k0;
+    const int g0 = a.gp_base[p];
+    const int nn[3] = {a.nx, a.ny, a.nz}, TT[3] = {a.TX, a.TY, a.TZ};
+    for (int kb = 0; kb < nk; kb += 64) {
+        // lane = patch kb + lane: its node range and tile count per axis
+        const int k = kb + lane;
+        int lo[3] = {0, 0, 0}, hi[3] = {0, 0, 0}, ncomb = 0;
+        if (k < nk) {
+            const double *bx = a.tp_box + 6 * (size_t)(k0 + k);
+            ncomb = 1;
+#pragma unroll
+            for (int d = 0; d < 3; ++d)
+                if (d < a.dim) {
+                    lo[d] = (int)floor(P.x[d] + bx[d]) - 1;
+                    hi[d] = (int)floor(P.x[d] + bx[3 + d]) + 2;
+                    ncomb *= axis_run(lo[d], hi[d], nn[d], a.per[d], TT[d]).cnt;
+                }
+        }
+        int incl = ncomb;
+#pragma unroll
+        for (int d = 1; d < 64; d <<= 1) {
+            const int y = __shfl_up(incl, d);
+            if (lane >= d) incl += y;
+        }
+        const int pre = incl - ncomb, tot = __shfl(incl, 63);
+        for (int f0 = 0; f0 < tot; f0 += 64) {
+            const int f = f0 + lane;
+            // the patch holding pair f: the last lane e with pre[e] <= f
+            int e = 0;
+#pragma unroll
+            for (int st = 32; st; st >>= 1) {
+                const int cand = e + st;
+                if (__shfl(pre, cand) <= f) e = cand;
+            }
+            int elo[3], ehi[3];
+#pragma unroll
+            for (int d = 0; d < 3; ++d) { elo[d] = __shfl(lo[d], e); ehi[d] = __shfl(hi[d], e); }
+            const int c = f - __shfl(pre, e);
+            if (f >= tot) continue;
+            AxisRun r[3] = {{0, 1, 1}, {0, 1, 1}, {0, 1, 1}};
+#pragma unroll
+            for (int d = 0; d < 3; ++d)
+                if (d < a.dim) r[d] = axis_run(elo[d], ehi[d], nn[d], a.per[d], TT[d]);
+            const int ix = c % r[0].cnt, iy = (c / r[0].cnt) % r[1].cnt, iz = c / (r[0].cnt * r[1].cnt);
+            const int t = (axis_tile(r[2], iz) * a.nty + axis_tile(r[1], iy)) * a.ntx + axis_tile(r[0], ix);
+            if (FILL) {
+                const int pos = atomicAdd(&a.tile_fill[t], 1);
+                const long long at = (long long)a.tile_start[t] + pos;
+                if (at < a.cap) a.tile_items[at] = g0 + kb + e;
+                else atomicOr(a.err, ERR_TILES);
+            } else {
+                atomicAdd(&a.tile_count[t], 1);
+            }
         }
     }
 }
