@@ -444,11 +444,15 @@ int hip_ok(pibm_ctx *c, hipError_t e)
     return PIBM_EDEVICE;
 }
 
+int build_cells(pibm_ctx *c);
+
 template <int DIM, class SF>
 int launch_markers(pibm_ctx *c, bool reactions)
 {
     using T = typename SF::T;
     if (c->P.np == 0) return PIBM_OK;
+    int st;
+    if ((st = build_cells(c))) return st;          // the order of the workgroups (the DEM reuses the list)
     MkArgs<T> m{};
     m.lb = lbm_args<T>(c);
     m.part = (const DevParticle *)c->r(c->pcur ? R_PART1 : R_PART0);
@@ -456,6 +460,7 @@ int launch_markers(pibm_ctx *c, bool reactions)
     m.tmpl_start = (const int *)c->r(R_TMPL_START);
     m.tmpl_rext = (const double *)c->r(R_TMPL_REXT);
     m.mk_start = (const int *)c->r(R_MK_START);
+    m.order = (const int *)c->r(R_CITEMS);
     m.mk = (MarkerRec<T> *)c->r(R_MK);
     m.react = reactions ? (DevReact *)c->r(R_REACT) : nullptr;
     m.kappa = c->p.kappa_T;
@@ -463,8 +468,6 @@ int launch_markers(pibm_ctx *c, bool reactions)
     hipLaunchKernelGGL((k_markers<DIM, SF>), dim3(c->P.np), dim3(256), 0, c->stream, m);
     return hip_ok(c, hipGetLastError());
 }
-
-int build_cells(pibm_ctx *c);
 
 template <int DIM, class SF>
 int launch_features(pibm_ctx *c, bool raw, bool for_network)
@@ -612,7 +615,6 @@ int launch_dem(pibm_ctx *c)
     int st;
     if ((st = build_cells(c))) return st;
     DemArgs a = dem_args(c);
-    const int gb = (c->P.np + 127) / 128;
     a.cur = (const DevParticle *)c->r(c->pcur ? R_PART1 : R_PART0);
     hipLaunchKernelGGL(k_neighbours, dim3((c->P.np + NBR_THREADS / 64 - 1) / (NBR_THREADS / 64)), dim3(NBR_THREADS), 0,
                        c->stream, a);
@@ -626,7 +628,7 @@ int launch_dem(pibm_ctx *c)
         a.hxi_out = (double *)c->r(c->hcur ? R_HXI0 : R_HXI1);
         a.hn_out = (int *)c->r(c->hcur ? R_HN0 : R_HN1);
         a.last = s == c->p.n_sub - 1;
-        hipLaunchKernelGGL(k_dem, dim3(gb), dim3(128), 0, c->stream, a);
+        hipLaunchKernelGGL(k_dem, dim3((c->P.np + 127) / 128), dim3(128), 0, c->stream, a);
         c->pcur ^= 1;
         c->hcur ^= 1;
         c->cells_ok = 0;
@@ -859,7 +861,7 @@ int pibm_init(pibm_ctx **out, const pibm_params *p, const pibm_particle *pt, int
     if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
     if (e != hipSuccess) { delete c; return PIBM_EDEVICE; }
     // zeroed small state: tile starts (no particles => empty lists), history counts, error word
-    const int zero_regions[] = {R_TSTART, R_TCOUNT, R_CCOUNT, R_CNTR, R_HN0, R_HN1, R_ERR, R_REACT};
+    const int zero_regions[] = {R_TSTART, R_TCOUNT, R_CCOUNT, R_CITEMS, R_CNTR, R_HN0, R_HN1, R_ERR, R_REACT};
     for (int r : zero_regions) {
         const size_t bytes = c->P.off[r + 1] - c->P.off[r];
         hipLaunchKernelGGL(k_fill_int, dim3(std::max<size_t>(1, std::min<size_t>(1024, (bytes / 4 + 255) / 256))), dim3(256), 0,

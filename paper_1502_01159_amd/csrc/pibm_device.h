@@ -769,6 +769,7 @@ template <typename T> struct MkArgs {
     const int *tmpl_start;
     const double *tmpl_rext;       // largest |r_l| component per template
     const int *mk_start;
+    const int *order;              // the particles in cell-list order (a permutation)
     MarkerRec<T> *mk;
     DevReact *react;               // NULL in the macro pass
     double kappa, Tref;
@@ -829,7 +830,13 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k
     __shared__ int cell[MAXSHELL];
     __shared__ T mom[DIM + 2][MAXSHELL];          // rho - 1, j, S - T_ref per stencil node
     __shared__ int s_total;
-    const int p = blockIdx.x, tid = threadIdx.x;
+    // Particles in cell-list order, in runs of consecutive ones per XCD (as
+    // the lattice tiles): neighbours' stencil rows share 128-byte lines, which
+    // are then fetched once into that XCD's L2.  Any permutation gives the
+    // same results; an index out of range (a list never built) falls back.
+    const int tid = threadIdx.x;
+    int p = a.order[xcd_tile(blockIdx.x, gridDim.x)];
+    if (p < 0 || p >= gridDim.x) p = blockIdx.x;
     // the particle's loads are issued before the halt check's barrier
     const DevParticle P = a.part[p];
     const int m0 = a.mk_start[p], nm = a.mk_start[p + 1] - m0;

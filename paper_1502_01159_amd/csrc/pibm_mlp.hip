@@ -8,7 +8,9 @@
 // the inputs (given as BF16), every weight, every hidden activation fed to the
 // next layer, the output gradient dL/dy and every pre-activation gradient fed
 // to a product.  Bias gradients are sums of those BF16 pre-activation
-// gradients; weight gradients are FP32 sums of BF16 x BF16 products.
+// gradients; weight gradients are FP32 sums of BF16 x BF16 products.  The
+// hidden units' erf is Hastings' rational approximation (|error| <= 1.5e-7);
+// the BF16 roundings are the hardware's round-to-nearest-even conversion.
 //
 // Layout.  Every layer is computed transposed, Y^T = W^T X^T, with 16 samples
 // along the product's N dimension: the 16x16 result tile of one product (lane
@@ -63,18 +65,59 @@ __host__ __device__ inline uint16_t bf16_rne(float f)
 }
 __device__ __forceinline__ float bf16_f(uint16_t b) { return __uint_as_float(((uint32_t)b) << 16); }
 
-__device__ __forceinline__ float gelu(float z) { return 0.5f * z * (1.0f + erff(z * 0.70710678118654752f)); }
+// erf(x) by Hastings' rational approximation (Abramowitz & Stegun 7.1.26):
+// erf(x) = 1 - t (a1 + t (a2 + t (a3 + t (a4 + t a5)))) exp(-x^2) with
+// t = 1 / (1 + p |x|), odd in x, |error| <= 1.5e-7 -- far below the BF16
+// rounding of the activations.  Branch-free (one reciprocal, one
+// exponential), unlike a library erff whose range split diverges across a
+// wave.  Also returns exp(-x^2).
+__device__ __forceinline__ float erf_hastings(float x, float &ex2)
+{
+    constexpr float p = 0.3275911f, a1 = 0.254829592f, a2 = -0.284496736f, a3 = 1.421413741f, a4 = -1.453152027f,
+                    a5 = 1.061405429f;
+    const float ax = fabsf(x);
+    const float t = __builtin_amdgcn_rcpf(fmaf(p, ax, 1.0f));
+    const float poly = t * fmaf(t, fmaf(t, fmaf(t, fmaf(t, a5, a4), a3), a2), a1);
+    ex2 = __expf(-ax * ax);
+    return copysignf(fmaf(-poly, ex2, 1.0f), x);
+}
+// GELU(z) = z Phi(z), Phi(z) = (1 + erf(z / sqrt 2)) / 2; GELU'(z) = Phi(z) + z phi(z)
+__device__ __forceinline__ float gelu(float z)
+{
+    float e;
+    return 0.5f * z * (1.0f + erf_hastings(z * 0.70710678118654752f, e));
+}
 __device__ __forceinline__ float gelu_d(float z)
 {
-    return 0.5f * (1.0f + erff(z * 0.70710678118654752f)) + z * 0.39894228040143268f * expf(-0.5f * z * z);
+    float e;
+    const float Phi = 0.5f * (1.0f + erf_hastings(z * 0.70710678118654752f, e));
+    return Phi + z * 0.39894228040143268f * e;
 }
 
 __device__ __forceinline__ v4f mfma(v4s a, v4s b, v4f c) { return __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, c, 0, 0, 0); }
+typedef __bf16 v8bf __attribute__((ext_vector_type(8)));
+typedef short v8s __attribute__((ext_vector_type(8)));
+// Two consecutive K = 16 products in one K = 32 product: lane group g holds
+// K positions 8g .. 8g + 7, here the first operands' 4g .. 4g + 3 followed by
+// the second's.  A and B share that order, so the result is a0 b0 + a1 b1.
+__device__ __forceinline__ v4f mfma2(v4s a0, v4s a1, v4s b0, v4s b1, v4f c)
+{
+    const v8s a = __builtin_shufflevector(a0, a1, 0, 1, 2, 3, 4, 5, 6, 7);
+    const v8s b = __builtin_shufflevector(b0, b1, 0, 1, 2, 3, 4, 5, 6, 7);
+    return __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(v8bf, a), __builtin_bit_cast(v8bf, b), c, 0, 0, 0);
+}
 __device__ __forceinline__ v4s lds4(const uint16_t *p) { return *(const v4s *)p; }
+typedef __bf16 v2bf __attribute__((ext_vector_type(2)));
+typedef float v2f __attribute__((ext_vector_type(2)));
+// four floats to BF16, round to nearest even (the hardware pack conversion)
 __device__ __forceinline__ v4s pack4(float a, float b, float c, float d)
 {
+    const v2bf lo = __builtin_convertvector((v2f){a, b}, v2bf), hi = __builtin_convertvector((v2f){c, d}, v2bf);
     v4s r;
-    r[0] = (short)bf16_rne(a); r[1] = (short)bf16_rne(b); r[2] = (short)bf16_rne(c); r[3] = (short)bf16_rne(d);
+    uint32_t u0, u1;
+    memcpy(&u0, &lo, 4);
+    memcpy(&u1, &hi, 4);
+    r[0] = (short)(u0 & 0xffffu); r[1] = (short)(u0 >> 16); r[2] = (short)(u1 & 0xffffu); r[3] = (short)(u1 >> 16);
     return r;
 }
 
@@ -102,8 +145,14 @@ __device__ __forceinline__ void layer_fwd(const uint16_t *w, int stride, const v
 #pragma unroll
     for (int m = 0; m < NH / 16; ++m) {
         v4f acc = {0.f, 0.f, 0.f, 0.f};
+        const uint16_t *wr = w + (16 * m + l16) * stride + 4 * g;
+        if (KT % 2 == 0) {
 #pragma unroll
-        for (int t = 0; t < KT; ++t) acc = mfma(lds4(w + (16 * m + l16) * stride + 16 * t + 4 * g), in[t], acc);
+            for (int t = 0; t < KT; t += 2) acc = mfma2(lds4(wr + 16 * t), lds4(wr + 16 * t + 16), in[t], in[t + 1], acc);
+        } else {
+#pragma unroll
+            for (int t = 0; t < KT; ++t) acc = mfma(lds4(wr + 16 * t), in[t], acc);
+        }
         z[m] = acc;
     }
 }
@@ -141,7 +190,8 @@ __global__ __launch_bounds__(MLP_THREADS) void k_mlp_fwd(MlpArgs a, const uint16
         }
         v4f o = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-        for (int t = 0; t < NH / 16; ++t) o = mfma(lds4(w + BW4 + l16 * PH + 16 * t + 4 * g), h[t], o);
+        for (int t = 0; t < NH / 16; t += 2)
+            o = mfma2(lds4(w + BW4 + l16 * PH + 16 * t + 4 * g), lds4(w + BW4 + l16 * PH + 16 * t + 16 + 4 * g), h[t], h[t + 1], o);
         if (g == 0 && s < n) {
             float4 r;
             r.x = o[0] + bias[3 * NH + 0]; r.y = o[1] + bias[3 * NH + 1];
@@ -204,7 +254,8 @@ __global__ __launch_bounds__(MLP_THREADS) void k_mlp_grad(MlpArgs a, const uint1
     }
     v4f o = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-    for (int t = 0; t < NH / 16; ++t) o = mfma(lds4(w + BW4 + l16 * PH + 16 * t + 4 * g), h[t], o);
+    for (int t = 0; t < NH / 16; t += 2)
+        o = mfma2(lds4(w + BW4 + l16 * PH + 16 * t + 4 * g), lds4(w + BW4 + l16 * PH + 16 * t + 16 + 4 * g), h[t], h[t + 1], o);
     // output gradient dL/dy = (y - t) / (2 n), zero for padding samples and rows
     double se = 0.0;
     float dy[4] = {0.f, 0.f, 0.f, 0.f};
@@ -245,9 +296,10 @@ __global__ __launch_bounds__(MLP_THREADS) void k_mlp_grad(MlpArgs a, const uint1
         for (int tt = wv; tt < ntm * ntn; tt += MLP_THREADS / 64) {
             const int ta = tt / ntn, tb = tt % ntn;
             v4f acc = {0.f, 0.f, 0.f, 0.f};
+            const uint16_t *ha = hs + (16 * ta + l16) * PS + 4 * g, *db = dz + (16 * tb + l16) * PS + 4 * g;
 #pragma unroll
-            for (int k = 0; k < SPB / 16; ++k)
-                acc = mfma(lds4(hs + (16 * ta + l16) * PS + 16 * k + 4 * g), lds4(dz + (16 * tb + l16) * PS + 16 * k + 4 * g), acc);
+            for (int k = 0; k < SPB / 16; k += 2)
+                acc = mfma2(lds4(ha + 16 * k), lds4(ha + 16 * k + 16), lds4(db + 16 * k), lds4(db + 16 * k + 16), acc);
             const int out = 16 * tb + l16;
             if (out < nout_real) {
 #pragma unroll
@@ -290,11 +342,14 @@ __global__ __launch_bounds__(MLP_THREADS) void k_mlp_grad(MlpArgs a, const uint1
             for (int m = 0; m < NH / 16; ++m) {
                 v4f acc = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-                for (int t = 0; t < NH / 16; ++t) {
-                    v4s A;
+                for (int t = 0; t < NH / 16; t += 2) {
+                    v4s A0, A1;
 #pragma unroll
-                    for (int kk = 0; kk < 4; ++kk) A[kk] = (short)wl[(16 * t + 4 * g + kk) * PH + 16 * m + l16];
-                    acc = mfma(A, dzb[t], acc);
+                    for (int kk = 0; kk < 4; ++kk) {
+                        A0[kk] = (short)wl[(16 * t + 4 * g + kk) * PH + 16 * m + l16];
+                        A1[kk] = (short)wl[(16 * t + 16 + 4 * g + kk) * PH + 16 * m + l16];
+                    }
+                    acc = mfma2(A0, A1, dzb[t], dzb[t + 1], acc);
                 }
                 dh[m] = acc;
             }
