@@ -170,6 +170,10 @@ __global__ __launch_bounds__(MLP_THREADS) void k_mlp_fwd(MlpArgs a, const uint16
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, l16 = lane & 15, g = lane >> 4;
     const int ntile = (n + 15) / 16;
     for (int tile = blockIdx.x * (MLP_THREADS / 64) + wv; tile < ntile; tile += gridDim.x * (MLP_THREADS / 64)) {
+        // keeps the weights' LDS reads inside the loop: hoisted, they would hold
+        // ~290 registers and allow one wave per SIMD; read per tile, two waves
+        // per SIMD overlap one's GELUs with the other's matrix products
+        asm volatile("" ::: "memory");
         const int s = tile * 16 + l16;
         v4s xb = {0, 0, 0, 0};
         if (s < n) xb = *(const v4s *)(x + (size_t)s * NI + 4 * g);
