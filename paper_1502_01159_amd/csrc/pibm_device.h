@@ -1089,16 +1089,18 @@ __global__ __launch_bounds__(FEAT_THREADS) void k_features(FeatArgs<typename SF:
     using C = double;
     using L = Lat<DIM>;
     constexpr int NN = DIM == 3 ? 4 : 6;
-    __shared__ double ssum[FEAT_THREADS / 64][6];
-    __shared__ double red_phi[FEAT_THREADS / 64];
-    __shared__ double wtop_d[FEAT_THREADS / 64][6], fin_d[6];
-    __shared__ int wtop_i[FEAT_THREADS / 64][6], fin_i[6];
-    const int p = blockIdx.x, tid = threadIdx.x;
+    // waves 0 .. MW - 1 sum the shell's moments while wave MW finds the
+    // neighbours; the two chains of loads overlap and meet at one barrier
+    constexpr int MW = FEAT_THREADS / 64 - 1;
+    __shared__ double ssum[MW][6];
+    __shared__ double s_vol;
+    __shared__ int fin_i[6];
+    const int p = blockIdx.x, tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
     if (block_halted(a.lb.err)) return;
     const DevParticle P = a.part[p];
     const int nn[3] = {a.lb.nx, a.lb.ny, a.lb.nz};
     const double D = 2.0 * P.R;
-    const double r_in = 0.75 * D, r_out = 1.5 * D;
+    const double r_in = 0.75 * D, r_out = 1.5 * D, rphi = 2.0 * D;
     // (1) raw moments summed over the shell's nodes, a fixed share per thread
     int lo[3] = {0, 0, 0}, ext[3] = {1, 1, 1};
 #pragma unroll
@@ -1110,178 +1112,164 @@ __global__ __launch_bounds__(FEAT_THREADS) void k_features(FeatArgs<typename SF:
 #pragma unroll
     for (int d = 0; d < DIM; ++d) sane = sane && ext[d] >= 1 && ext[d] <= 4096;
     const int nbox = sane ? ext[0] * ext[1] * ext[2] : 0;   // non-finite centre: empty shell
-    double sm[5] = {0, 0, 0, 0, 0};               // rho, j, S - T_ref
-    double cnt = 0.0;
-    for (int o = tid; o < nbox; o += FEAT_THREADS) {
-        int c[3] = {0, 0, 0};
-        double r2 = 0.0;
-        bool ok = true;
-        int oo = o;
+    if (wv < MW) {
+        double sm[5] = {0, 0, 0, 0, 0};               // rho, j, S - T_ref
+        double cnt = 0.0;
+        for (int o = tid; o < nbox; o += 64 * MW) {
+            int c[3] = {0, 0, 0};
+            double r2 = 0.0;
+            bool ok = true;
+            int oo = o;
 #pragma unroll
-        for (int d = 0; d < DIM; ++d) {
-            const int v0 = lo[d] + oo % ext[d];
-            oo /= ext[d];
-            const double dx = v0 - P.x[d];
-            r2 += dx * dx;
-            int v = v0;
-            if (a.lb.per[d]) { v %= nn[d]; if (v < 0) v += nn[d]; }
-            else if (v < 0 || v >= nn[d]) ok = false;
-            c[d] = v;
-        }
-        if (!ok || r2 < r_in * r_in || r2 > r_out * r_out) continue;
-        T f[L::Q];
-        C g[L::QG];
-        pull<DIM, SF, T, C>(a.lb, c[0], c[1], c[2], f, g);
-        C drho, j[3], dS;
-        moments<DIM, C>(f, g, drho, j, dS);
-        sm[0] += 1.0 + drho; sm[1] += j[0]; sm[2] += j[1]; sm[3] += j[2]; sm[4] += dS;
-        cnt += 1.0;
-    }
-#pragma unroll
-    for (int off = 32; off; off >>= 1) {
-#pragma unroll
-        for (int q = 0; q < 5; ++q) sm[q] += __shfl_xor(sm[q], off);
-        cnt += __shfl_xor(cnt, off);
-    }
-    if ((tid & 63) == 0) {
-#pragma unroll
-        for (int q = 0; q < 5; ++q) ssum[tid >> 6][q] = sm[q];
-        ssum[tid >> 6][5] = cnt;
-    }
-    // (2) neighbours.  Every centre within 2 D lies in the 5^d cells around
-    // the particle's own (a cell is wider than any diameter), so the solid
-    // volume comes from those cells alone.  Their nearest NN (by distance,
-    // then index) are the nearest of all particles when the NN-th is closer
-    // than two cell widths, the least distance of any centre outside them;
-    // otherwise the nearest are searched again over all particles.
-    const double rphi = 2.0 * D;
-    double bd[6];
-    int bi[6];
-    auto clear = [&]() {
-#pragma unroll
-        for (int q = 0; q < 6; ++q) { bd[q] = 1e300; bi[q] = 0x7fffffff; }
-    };
-    auto offer = [&](int jn, double &vol) {
-        const DevParticle Q = a.part[jn];
-        double d2 = 0.0;
-#pragma unroll
-        for (int d = 0; d < DIM; ++d) {
-            double dx = Q.x[d] - P.x[d];
-            if (a.lb.per[d]) dx -= nn[d] * rint(dx / nn[d]);
-            d2 += dx * dx;
-        }
-        if (d2 < rphi * rphi)
-            vol += DIM == 3 ? (4.0 / 3.0) * M_PI * Q.R * Q.R * Q.R : M_PI * Q.R * Q.R;
-        if (jn == p) return;
-        if (d2 < bd[NN - 1] || (d2 == bd[NN - 1] && jn < bi[NN - 1])) {   // sorted insert
-            int q = NN - 1;
-            while (q > 0 && (d2 < bd[q - 1] || (d2 == bd[q - 1] && jn < bi[q - 1]))) {
-                bd[q] = bd[q - 1]; bi[q] = bi[q - 1];
-                --q;
+            for (int d = 0; d < DIM; ++d) {
+                const int v0 = lo[d] + oo % ext[d];
+                oo /= ext[d];
+                const double dx = v0 - P.x[d];
+                r2 += dx * dx;
+                int v = v0;
+                if (a.lb.per[d]) { v %= nn[d]; if (v < 0) v += nn[d]; }
+                else if (v < 0 || v >= nn[d]) ok = false;
+                c[d] = v;
             }
-            bd[q] = d2; bi[q] = jn;
+            if (!ok || r2 < r_in * r_in || r2 > r_out * r_out) continue;
+            T f[L::Q];
+            C g[L::QG];
+            pull<DIM, SF, T, C>(a.lb, c[0], c[1], c[2], f, g);
+            C drho, j[3], dS;
+            moments<DIM, C>(f, g, drho, j, dS);
+            sm[0] += 1.0 + drho; sm[1] += j[0]; sm[2] += j[1]; sm[3] += j[2]; sm[4] += dS;
+            cnt += 1.0;
         }
-    };
-    // block-wide nearest NN of the threads' sorted lists: NN rounds of a wave
-    // minimum over the list heads, then thread 0 merges the waves' picks
-    auto select = [&]() {
-        for (int r = 0; r < NN; ++r) {
-            double md = bd[0];
-            int mi = bi[0];
 #pragma unroll
-            for (int off = 32; off; off >>= 1) {
-                const double od = __shfl_xor(md, off);
-                const int oi = __shfl_xor(mi, off);
-                if (od < md || (od == md && oi < mi)) { md = od; mi = oi; }
-            }
-            if ((tid & 63) == 0) { wtop_d[tid >> 6][r] = md; wtop_i[tid >> 6][r] = mi; }
-            if (bd[0] == md && bi[0] == mi) {
+        for (int off = 32; off; off >>= 1) {
 #pragma unroll
-                for (int q = 0; q < 5; ++q) { bd[q] = bd[q + 1]; bi[q] = bi[q + 1]; }
-                bd[5] = 1e300; bi[5] = 0x7fffffff;
-            }
+            for (int q = 0; q < 5; ++q) sm[q] += __shfl_xor(sm[q], off);
+            cnt += __shfl_xor(cnt, off);
         }
-        __syncthreads();
-        if (tid == 0) {
-            double nd[6];
-            int ni[6];
+        if (lane == 0) {
 #pragma unroll
-            for (int q = 0; q < 6; ++q) { nd[q] = 1e300; ni[q] = 0x7fffffff; }
-            for (int c2 = 0; c2 < (FEAT_THREADS / 64) * NN; ++c2) {
-                const double d2 = wtop_d[c2 / NN][c2 % NN];
-                const int jn = wtop_i[c2 / NN][c2 % NN];
-                if (d2 < nd[NN - 1] || (d2 == nd[NN - 1] && jn < ni[NN - 1])) {
-                    int q = NN - 1;
-                    while (q > 0 && (d2 < nd[q - 1] || (d2 == nd[q - 1] && jn < ni[q - 1]))) {
-                        nd[q] = nd[q - 1]; ni[q] = ni[q - 1];
-                        --q;
-                    }
-                    nd[q] = d2; ni[q] = jn;
+            for (int q = 0; q < 5; ++q) ssum[wv][q] = sm[q];
+            ssum[wv][5] = cnt;
+        }
+    } else {
+        // (2) neighbours.  Every centre within 2 D lies in the 5^d cells around
+        // the particle's own (a cell is wider than any diameter), so the solid
+        // volume comes from those cells alone.  Their nearest NN (by distance,
+        // then index) are the nearest of all particles when the NN-th is closer
+        // than two cell widths, the least distance of any centre outside them;
+        // otherwise the nearest are searched again over all particles.
+        double bd[6];
+        int bi[6];
+        auto clear = [&]() {
+#pragma unroll
+            for (int q = 0; q < 6; ++q) { bd[q] = 1e300; bi[q] = 0x7fffffff; }
+        };
+        auto offer = [&](int jn, double &vol) {
+            const DevParticle Q = a.part[jn];
+            double d2 = 0.0;
+#pragma unroll
+            for (int d = 0; d < DIM; ++d) {
+                double dx = Q.x[d] - P.x[d];
+                if (a.lb.per[d]) dx -= nn[d] * rint(dx / nn[d]);
+                d2 += dx * dx;
+            }
+            if (d2 < rphi * rphi)
+                vol += DIM == 3 ? (4.0 / 3.0) * M_PI * Q.R * Q.R * Q.R : M_PI * Q.R * Q.R;
+            if (jn == p) return;
+            if (d2 < bd[NN - 1] || (d2 == bd[NN - 1] && jn < bi[NN - 1])) {   // sorted insert
+                int q = NN - 1;
+                while (q > 0 && (d2 < bd[q - 1] || (d2 == bd[q - 1] && jn < bi[q - 1]))) {
+                    bd[q] = bd[q - 1]; bi[q] = bi[q - 1];
+                    --q;
+                }
+                bd[q] = d2; bi[q] = jn;
+            }
+        };
+        // nearest NN of the lanes' sorted lists: NN rounds of a wave minimum over
+        // the list heads; every lane ends with the same nd, ni
+        double nd[6];
+        int ni[6];
+        auto select = [&]() {
+            for (int r = 0; r < NN; ++r) {
+                double md = bd[0];
+                int mi = bi[0];
+#pragma unroll
+                for (int off = 32; off; off >>= 1) {
+                    const double od = __shfl_xor(md, off);
+                    const int oi = __shfl_xor(mi, off);
+                    if (od < md || (od == md && oi < mi)) { md = od; mi = oi; }
+                }
+                nd[r] = md; ni[r] = mi;
+                if (bd[0] == md && bi[0] == mi) {
+#pragma unroll
+                    for (int q = 0; q < 5; ++q) { bd[q] = bd[q + 1]; bi[q] = bi[q + 1]; }
+                    bd[5] = 1e300; bi[5] = 0x7fffffff;
                 }
             }
-            for (int q = 0; q < NN; ++q) { fin_d[q] = nd[q]; fin_i[q] = ni[q]; }
-        }
-        __syncthreads();
-    };
-    constexpr int KR = 2;
-    const int nc[3] = {a.ncx, a.ncy, DIM == 3 ? a.ncz : 1};
-    const double cw[3] = {a.cwx, a.cwy, a.cwz};
-    bool centred = true;
+        };
+        constexpr int KR = 2;
+        const int nc[3] = {a.ncx, a.ncy, DIM == 3 ? a.ncz : 1};
+        const double cw[3] = {a.cwx, a.cwy, a.cwz};
+        bool centred = true;
 #pragma unroll
-    for (int d = 0; d < DIM; ++d) centred = centred && isfinite(P.x[d]);
-    int c0[3] = {0, 0, 0}, span[3] = {1, 1, 1};
-    bool full[3] = {true, true, true};
-    double bound = 1e300;                          // least distance of a centre outside the cells scanned
-    if (centred) {
+        for (int d = 0; d < DIM; ++d) centred = centred && isfinite(P.x[d]);
+        int c0[3] = {0, 0, 0}, span[3] = {1, 1, 1};
+        bool full[3] = {true, true, true};
+        double bound = 1e300;                          // least distance of a centre outside the cells scanned
+        if (centred) {
 #pragma unroll
-        for (int d = 0; d < DIM; ++d) {
-            c0[d] = cell_coord(P.x[d], nn[d], a.lb.per[d], nc[d], cw[d]);
-            full[d] = a.lb.per[d] && 2 * KR + 1 >= nc[d];
-            span[d] = full[d] ? nc[d] : 2 * KR + 1;
-            if (!full[d]) bound = fmin(bound, KR * cw[d] * (1.0 - 1e-9));
-        }
-    }
-    double vol = 0.0;
-    clear();
-    const int ncs = centred ? span[0] * span[1] * span[2] : 0;
-    for (int k = tid; k < ncs; k += FEAT_THREADS) {
-        int o[3] = {k % span[0], (k / span[0]) % span[1], k / (span[0] * span[1])};
-        int cell = 0;
-        bool ok = true;
-#pragma unroll
-        for (int d = 2; d >= 0; --d) {
-            int m = o[d];
-            if (!full[d]) {
-                m = c0[d] + o[d] - KR;
-                if (a.lb.per[d]) { m %= nc[d]; if (m < 0) m += nc[d]; }
-                else ok = ok && m >= 0 && m < nc[d];
+            for (int d = 0; d < DIM; ++d) {
+                c0[d] = cell_coord(P.x[d], nn[d], a.lb.per[d], nc[d], cw[d]);
+                full[d] = a.lb.per[d] && 2 * KR + 1 >= nc[d];
+                span[d] = full[d] ? nc[d] : 2 * KR + 1;
+                if (!full[d]) bound = fmin(bound, KR * cw[d] * (1.0 - 1e-9));
             }
-            cell = cell * nc[d] + m;
         }
-        if (!ok) continue;
-        const int s0 = a.cell_start[cell], e0 = s0 + a.cell_count[cell];
-        for (int it = s0; it < e0; ++it) offer(a.cell_items[it], vol);
-    }
-#pragma unroll
-    for (int off = 32; off; off >>= 1) vol += __shfl_xor(vol, off);
-    if ((tid & 63) == 0) red_phi[tid >> 6] = vol;
-    select();
-    const bool all_scanned = centred && full[0] && full[1] && full[2];
-    const bool exact = all_scanned || (fin_i[NN - 1] != 0x7fffffff && fin_d[NN - 1] < bound * bound);
-    if (!exact) {
-        double dummy = 0.0;
+        double vol = 0.0;
         clear();
-        for (int jn = tid; jn < a.np; jn += FEAT_THREADS) offer(jn, dummy);
+        const int ncs = centred ? span[0] * span[1] * span[2] : 0;
+        for (int k = lane; k < ncs; k += 64) {
+            int o[3] = {k % span[0], (k / span[0]) % span[1], k / (span[0] * span[1])};
+            int cell = 0;
+            bool ok = true;
+#pragma unroll
+            for (int d = 2; d >= 0; --d) {
+                int m = o[d];
+                if (!full[d]) {
+                    m = c0[d] + o[d] - KR;
+                    if (a.lb.per[d]) { m %= nc[d]; if (m < 0) m += nc[d]; }
+                    else ok = ok && m >= 0 && m < nc[d];
+                }
+                cell = cell * nc[d] + m;
+            }
+            if (!ok) continue;
+            const int s0 = a.cell_start[cell], e0 = s0 + a.cell_count[cell];
+            for (int it = s0; it < e0; ++it) offer(a.cell_items[it], vol);
+        }
+#pragma unroll
+        for (int off = 32; off; off >>= 1) vol += __shfl_xor(vol, off);
         select();
+        const bool all_scanned = centred && full[0] && full[1] && full[2];
+        const bool exact = all_scanned || (ni[NN - 1] != 0x7fffffff && nd[NN - 1] < bound * bound);
+        if (!exact) {
+            double dummy = 0.0;
+            clear();
+            for (int jn = lane; jn < a.np; jn += 64) offer(jn, dummy);
+            select();
+        }
+        if (lane == 0) {
+            s_vol = vol;
+            for (int q = 0; q < NN; ++q) fin_i[q] = ni[q];
+        }
     }
+    __syncthreads();
     if (tid != 0) return;
     int ni[6];
     for (int q = 0; q < NN; ++q) ni[q] = fin_i[q];
-    double vtot = 0.0;
-    for (int w = 0; w < FEAT_THREADS / 64; ++w) vtot += red_phi[w];
+    const double vtot = s_vol;
     // (3) fluid seen by the particle (waves summed in a fixed order)
     double tot[6] = {0, 0, 0, 0, 0, 0};
-    for (int w = 0; w < FEAT_THREADS / 64; ++w)
+    for (int w = 0; w < MW; ++w)
 #pragma unroll
         for (int q = 0; q < 6; ++q) tot[q] += ssum[w][q];
     const double irho = tot[0] > 0 ? 1.0 / tot[0] : 0.0;
