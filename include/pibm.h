@@ -34,7 +34,7 @@ typedef struct pibm_ctx pibm_ctx;
 typedef enum {
     PIBM_OK = 0,
     PIBM_EINVAL = -1,    /* bad parameter, size, pointer or workspace too small */
-    PIBM_ENOMEM = -2,    /* a device-side capacity (contacts, neighbours) was exceeded */
+    PIBM_ENOMEM = -2,    /* a device-side capacity (contacts, neighbours, tile lists) was exceeded */
     PIBM_EDEVICE = -3,   /* a HIP runtime call failed; the context must be destroyed */
     PIBM_EUNSTABLE = -4, /* the device watchdog saw a NaN, |u| > 0.4, a stale neighbour list
                             or a particle outside the domain */
