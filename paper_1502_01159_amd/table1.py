@@ -1,0 +1,89 @@
+"""Table 1 of the paper (Sec. 3.1) on the GPU: the average Nusselt number of
+a square cavity with cold walls (T = 0) around a concentric isothermal
+cylinder (T = 1), fluid initially at T = 0.5, Pr = 0.71, for Ra in
+{1e4, 1e5, 1e6} and aspect ratio Ar = L / D in {5, 2.5, 1.67}, run to a
+steady state.
+
+Nu = sum_l (T_p - T_l) A_l / (alpha (T_hot - T_cold)) (Sec. 3.1), i.e. the
+cylinder's reaction sum (T_p - T_l) A_l over alpha, with T_hot - T_cold = 1.
+
+    python -m paper_1502_01159_amd.table1 [--n 250] [--cases all|Ra,Ar;...]
+
+Every number is computed by the library's kernels; this module only steps
+the runs and reads the reactions.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import sys
+import time
+
+from . import workloads as W
+
+# "Present" column of Table 1 (Sec. 3.1): (Ra, Ar) -> Nu on a 250 x 250 mesh
+PRINTED = {
+    (1e4, 5.0): 2.041, (1e4, 2.5): 3.179, (1e4, 1.67): 5.213,
+    (1e5, 5.0): 3.760, (1e5, 2.5): 4.989, (1e5, 1.67): 6.193,
+    (1e6, 5.0): 6.025, (1e6, 2.5): 8.831, (1e6, 1.67): 11.857,
+}
+
+
+def nusselt(sim) -> float:
+    _, fth = sim.particles()
+    return float(fth[0, 7] / sim.derived["alpha"])
+
+
+def run_case(pibm, n: int, Ra: float, Ar: float, storage: str = "f32", chunk: int = 5000, tol: float = 1e-4,
+             max_steps: int = 600000, log=None):
+    """Steps until Nu changes by less than tol (relative) over two consecutive
+    chunks, or max_steps.  Returns (Nu, steps, converged, seconds)."""
+    cfg, P = W.annulus_2d(n=n, Ra=Ra, Ar=Ar)
+    sim = pibm.Simulation(cfg, P, storage=storage)
+    t0 = time.perf_counter()
+    hist = []
+    steps = 0
+    converged = False
+    try:
+        while steps < max_steps:
+            sim.step(chunk)
+            steps += chunk
+            hist.append(nusselt(sim))
+            if log is not None and len(hist) % 10 == 0:
+                log(f"  Ra={Ra:g} Ar={Ar:g}: {steps} steps, Nu={hist[-1]:.5f}")
+            if len(hist) >= 3 and all(abs(hist[-1 - k] - hist[-2 - k]) <= tol * abs(hist[-1]) for k in range(2)):
+                converged = True
+                break
+        return hist[-1], steps, converged, time.perf_counter() - t0
+    finally:
+        sim.close()
+
+
+def main(argv=None) -> int:
+    ap = argparse.ArgumentParser(description=__doc__.split("\n\n")[0])
+    ap.add_argument("--n", type=int, default=250, help="lattice side (the paper's mesh is 250)")
+    ap.add_argument("--cases", default="all", help='"all" or "Ra,Ar;Ra,Ar;..."')
+    ap.add_argument("--storage", default="f32")
+    ap.add_argument("--chunk", type=int, default=5000)
+    ap.add_argument("--tol", type=float, default=1e-4)
+    ap.add_argument("--max-steps", type=int, default=600000)
+    args = ap.parse_args(argv)
+    from . import pibm
+
+    cases = list(PRINTED) if args.cases == "all" else [
+        tuple(float(v) for v in c.split(",")) for c in args.cases.split(";")]
+    log = lambda m: print(m, flush=True)
+    rows = []
+    for Ra, Ar in cases:
+        nu, steps, ok, sec = run_case(pibm, args.n, Ra, Ar, args.storage, args.chunk, args.tol, args.max_steps, log)
+        ref = PRINTED.get((Ra, Ar))
+        row = dict(Ra=Ra, Ar=Ar, n=args.n, Nu=round(nu, 4), printed=ref,
+                   rel_err=None if ref is None else round(nu / ref - 1.0, 4), steps=steps, converged=ok,
+                   seconds=round(sec, 1))
+        rows.append(row)
+        log(json.dumps(row))
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

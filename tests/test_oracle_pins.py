@@ -516,3 +516,23 @@ def test_conduction_annulus_nusselt_vs_laplace(oracle_mod):
     o2.step(4000)
     nu_lit = o2.reactions()[0, 7] / o2.derived["alpha"]
     assert abs(nu_lit - ref) > 0.1 * ref
+
+
+def test_table1_steady_nusselt_64():
+    """P8: the Table 1 case Ra = 1e4, Ar = 2.5 (Sec. 3.1) run to a steady
+    state on a 64^2 lattice.  Nu is within 5% of the printed 3.179 (the
+    paper's mesh is 250^2), and the stored oracle value the GPU tests compare
+    with reproduces."""
+    import importlib.util
+    import os
+
+    here = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+    spec = importlib.util.spec_from_file_location("make_table1_oracle", os.path.join(here, "make_table1_oracle.py"))
+    mod = importlib.util.module_from_spec(spec)
+    spec.loader.exec_module(mod)
+    nu, steps = mod.steady_nusselt()
+    printed = {(float(r), float(a)): float(v) for r, a, v in
+               (l.split() for l in open(os.path.join(here, "table1_nu.txt")) if l.strip() and not l.startswith("#"))}
+    assert abs(nu / printed[(1e4, 2.5)] - 1.0) <= 0.05, nu
+    stored = float([l for l in open(os.path.join(here, "table1_oracle_64.txt")) if not l.startswith("#")][0])
+    assert abs(nu - stored) <= 1e-9 * abs(stored), (nu, stored)
