@@ -98,6 +98,9 @@ typedef struct pibm_params {
     double beta_p;           /* thermosensitive particles: rho_p(T) = rho_r (1 - beta_p (T - T_ref)) */
     double c_r;              /* particle / fluid volumetric heat-capacity ratio */
     double skin;             /* DEM neighbour-list skin (lu); <= 0 means 1 */
+    int interp_order;        /* Lagrange nodes per axis of the interpolation, Eq. (lbm6): 2 (the
+                                cell's corners, multilinear; 0 means 2) or 4 (nodes floor(X) - 1 ..
+                                floor(X) + 2, cubic); other values are PIBM_EINVAL */
 } pibm_params;
 
 enum { PIBM_FIXED = 1, PIBM_THERMO = 2 };

@@ -38,6 +38,7 @@ class OrcParams(ctypes.Structure):
         ("n_sub", ctypes.c_int),
         ("beta_p", ctypes.c_double), ("c_r", ctypes.c_double),
         ("marker_mode", ctypes.c_int), ("marker_spacing", ctypes.c_double),
+        ("interp_order", ctypes.c_int),
     ]
 
 
@@ -142,6 +143,7 @@ def make_params(cfg: dict) -> OrcParams:
     p.beta_p = cfg.get("beta_p", 0.0)
     p.c_r = cfg.get("c_r", 1.0)
     p.marker_mode = int(cfg.get("marker_mode", 0))
+    p.interp_order = int(cfg.get("interp_order", 2))
     p.marker_spacing = cfg.get("marker_spacing", 1.0)
     return p
 

@@ -18,7 +18,7 @@
  *      -- Sec. 2.1, Eqs. (lbm2), (lbm2.5);
  *   2. raw moments rho = sum f, j = sum e f, S = sum g        -- Sec. 2.1;
  *   3. Lagrange interpolation of rho, j, S to the Lagrangian points
- *      -- Sec. 2.2, Eqs. (lbm5), (lbm5.5), (lbm6) with i_max = 2;
+ *      -- Sec. 2.2, Eqs. (lbm5), (lbm5.5), (lbm6) with i_max = 2 (or 4);
  *   4. point exchange F_l = 2(rho_l U_l - j_l), Q_l = 2 kappa (T_p - T_l)
  *      -- Sec. 2.2, Eqs. (lbm7), (lbm7.5), (lbm8) summed over directions;
  *   5. per-particle reactions  F = -sum F_l A_l, tau = -sum r x F_l A_l,
@@ -61,6 +61,7 @@ typedef struct {
     double beta_p, c_r;      /* thermosensitive density slope, heat-capacity ratio */
     int marker_mode;         /* 0 surface element, 1 A = pi s^2/4, 2 one point */
     double marker_spacing;
+    int interp_order;        /* Lagrange nodes per axis in Eq. (lbm6): 2 (0 means 2) or 4 */
 } orc_params;
 
 enum { ORC_FIXED = 1, ORC_THERMO = 2 };
@@ -453,24 +454,53 @@ static void pibm(orc_state *s, int record_reactions)
             U[1] = q->u[1] + q->om[2]*r[0] - q->om[0]*r[2];
             U[2] = q->u[2] + q->om[0]*r[1] - q->om[1]*r[0];
             if (dim == 2) { X[2] = 0; U[2] = 0; }
-            /* Eq. (lbm6) with i_max = j_max = k_max = 2: multilinear weights on
-             * the corners of the lattice cell holding X_l. */
             int b[3]; double t[3];
             for (int d = 0; d < 3; d++) { b[d] = (int)floor(X[d]); t[d] = X[d] - b[d]; }
             double rl = 0, jl[3] = {0, 0, 0}, Tl = 0;
-            int nc = dim == 2 ? 4 : 8;
-            for (int c = 0; c < nc; c++) {
-                int o[3] = {c & 1, (c >> 1) & 1, (c >> 2) & 1};
-                double W = 1.0;
-                int idx[3] = {0, 0, 0};
-                for (int d = 0; d < dim; d++) {
-                    W *= o[d] ? t[d] : 1.0 - t[d];
-                    idx[d] = clamp_coord(s, d, b[d] + o[d]);
+            if (s->p.interp_order == 4) {
+                /* Eq. (lbm6) with i_max = j_max = k_max = 4: the tensor product
+                 * of the cubic Lagrange polynomials through the nodes
+                 * b - 1 .. b + 2 of each axis, l_k(t) = prod_{m != k}
+                 * (t - m) / (k - m) over k, m in {-1, 0, 1, 2}. */
+                double L[3][4];
+                for (int d = 0; d < 3; d++)
+                    for (int k = 0; k < 4; k++) {
+                        double w = 1.0;
+                        for (int m = 0; m < 4; m++)
+                            if (m != k) w *= (t[d] - (m - 1)) / (double)(k - m);
+                        L[d][k] = w;
+                    }
+                int nc = dim == 2 ? 16 : 64;
+                for (int c = 0; c < nc; c++) {
+                    int o[3] = {c & 3, (c >> 2) & 3, (c >> 4) & 3};
+                    double W = 1.0;
+                    int idx[3] = {0, 0, 0};
+                    for (int d = 0; d < dim; d++) {
+                        W *= L[d][o[d]];
+                        idx[d] = clamp_coord(s, d, b[d] - 1 + o[d]);
+                    }
+                    long n = node_index(s, idx[0], idx[1], idx[2]);
+                    rl += W * s->rho[n];
+                    for (int d = 0; d < 3; d++) jl[d] += W * s->j[3*n + d];
+                    Tl += W * s->S[n];
                 }
-                long n = node_index(s, idx[0], idx[1], idx[2]);
-                rl += W * s->rho[n];
-                for (int d = 0; d < 3; d++) jl[d] += W * s->j[3*n + d];
-                Tl += W * s->S[n];
+            } else {
+                /* Eq. (lbm6) with i_max = j_max = k_max = 2: multilinear weights on
+                 * the corners of the lattice cell holding X_l. */
+                int nc = dim == 2 ? 4 : 8;
+                for (int c = 0; c < nc; c++) {
+                    int o[3] = {c & 1, (c >> 1) & 1, (c >> 2) & 1};
+                    double W = 1.0;
+                    int idx[3] = {0, 0, 0};
+                    for (int d = 0; d < dim; d++) {
+                        W *= o[d] ? t[d] : 1.0 - t[d];
+                        idx[d] = clamp_coord(s, d, b[d] + o[d]);
+                    }
+                    long n = node_index(s, idx[0], idx[1], idx[2]);
+                    rl += W * s->rho[n];
+                    for (int d = 0; d < 3; d++) jl[d] += W * s->j[3*n + d];
+                    Tl += W * s->S[n];
+                }
             }
             /* Eqs. (lbm7)-(lbm8): bouncing every direction back at the point
              * and summing e_beta (f_beta - f_alpha) gives 2(rho_l U_l - j_l).

@@ -165,6 +165,7 @@ int check_params(const pibm_params *p)
     if (p->storage < PIBM_STORE_F32 || p->storage > PIBM_STORE_BF16DEV) return PIBM_EINVAL;
     if (p->marker_mode < 0 || p->marker_mode > 2) return PIBM_EINVAL;
     if (p->n_sub < 1) return PIBM_EINVAL;
+    if (p->interp_order != 0 && p->interp_order != 2 && p->interp_order != 4) return PIBM_EINVAL;
     const Derived d = derive(*p);
     if (!(d.tau_f > 0.5) || !(d.tau_g > 0.5)) return PIBM_EINVAL;
     if (!std::isfinite(d.gbeta)) return PIBM_EINVAL;
@@ -470,7 +471,10 @@ int launch_markers(pibm_ctx *c, bool reactions)
     m.react = reactions ? (DevReact *)c->r(R_REACT) : nullptr;
     m.kappa = c->p.kappa_T;
     m.Tref = c->p.T_ref;
-    hipLaunchKernelGGL((k_markers<DIM, SF>), dim3(c->P.np), dim3(256), 0, c->stream, m);
+    if (c->p.interp_order == 4)
+        hipLaunchKernelGGL((k_markers<DIM, SF, 4>), dim3(c->P.np), dim3(256), 0, c->stream, m);
+    else
+        hipLaunchKernelGGL((k_markers<DIM, SF, 2>), dim3(c->P.np), dim3(256), 0, c->stream, m);
     return hip_ok(c, hipGetLastError());
 }
 

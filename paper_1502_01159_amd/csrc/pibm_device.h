@@ -816,7 +816,23 @@ constexpr int K2_MAXBOX = 16384;    // cells of a particle's stencil box (bitmap
 // directly); sized so that several workgroups share a CU
 template <class T> struct K2Shell { static constexpr int MAX = sizeof(T) == 8 ? 1024 : 1280; };
 
-template <int DIM, class SF>
+// Cubic Lagrange weights of Eq. (lbm6) (i_max = 4) on one axis for a point
+// at fraction t of its cell: the nodes b - 1 .. b + 2, l_k(t) = prod_{m != k}
+// (t - m) / (k - m) over k, m in {-1, 0, 1, 2}.  (i_max = 2 is 1 - t, t.)
+template <int IM>
+__device__ __forceinline__ void lagrange_weights(double t, double *w)
+{
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        double v = 1.0;
+#pragma unroll
+        for (int m = 0; m < 4; ++m)
+            if (m != k) v *= (t - (m - 1)) / (double)(k - m);
+        w[k] = v;
+    }
+}
+
+template <int DIM, class SF, int IM>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k_markers(MkArgs<typename SF::T> a)
 {
     using T = typename SF::T;
@@ -844,12 +860,15 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k
     const int t0 = a.tmpl_start[P.tmpl];
     const int nn[3] = {a.lb.nx, a.lb.ny, a.lb.nz};
 
-    // Stencil box: the cells floor(X_l) and floor(X_l) + 1 of every point.
+    // Stencil box: the nodes floor(X_l) - LO .. floor(X_l) - LO + IM - 1 of
+    // every point (IM Lagrange nodes per axis, Eq. lbm6).
+    constexpr int LO = IM == 4 ? 1 : 0;
+    constexpr int NCOR = DIM == 3 ? IM * IM * IM : IM * IM;
     const double re = a.tmpl_rext[P.tmpl];
     int bo[3] = {0, 0, 0}, bs[3] = {1, 1, 1};
     for (int d = 0; d < DIM; ++d) {
-        bo[d] = (int)floor(P.x[d] - re);
-        bs[d] = (int)floor(P.x[d] + re) + 2 - bo[d];
+        bo[d] = (int)floor(P.x[d] - re) - LO;
+        bs[d] = (int)floor(P.x[d] + re) - LO + IM - bo[d];
     }
     const int nbox = bs[0] * bs[1] * bs[2];
     const int nwords = (nbox + 31) / 32;
@@ -863,9 +882,9 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k
             const double4 r4 = a.tmpl[t0 + m];
             const double r[3] = {r4.x, r4.y, r4.z};
             int u[3] = {0, 0, 0};
-            for (int d = 0; d < DIM; ++d) u[d] = (int)floor(P.x[d] + r[d]) - bo[d];
-            for (int c = 0; c < (1 << DIM); ++c) {
-                const int cx = u[0] + (c & 1), cy = u[1] + ((c >> 1) & 1), cz = u[2] + ((c >> 2) & 1);
+            for (int d = 0; d < DIM; ++d) u[d] = (int)floor(P.x[d] + r[d]) - LO - bo[d];
+            for (int c = 0; c < NCOR; ++c) {
+                const int cx = u[0] + c % IM, cy = u[1] + (c / IM) % IM, cz = u[2] + (DIM == 3 ? c / (IM * IM) : 0);
                 const int lin = (cz * bs[1] + cy) * bs[0] + cx;
                 atomicOr(&bits[lin >> 5], 1u << (lin & 31));
             }
@@ -936,23 +955,27 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k
         // differences of O(1) numbers, and their rounding would act as a
         // systematic source every step.
         double rl = 0, jl[3] = {0, 0, 0}, sl = 0;
-#pragma unroll 1
-        for (int c = 0; c < (1 << DIM); ++c) {
-            double W = 1;
-            int o[3] = {c & 1, (c >> 1) & 1, (c >> 2) & 1};
+        double lw[3][IM];
+        if (IM != 2)
 #pragma unroll
-            for (int d = 0; d < DIM; ++d) W *= o[d] ? tt[d] : 1.0 - tt[d];
+            for (int d = 0; d < DIM; ++d) lagrange_weights<IM>(tt[d], lw[d]);
+#pragma unroll 1
+        for (int c = 0; c < NCOR; ++c) {
+            double W = 1;
+            const int o[3] = {c % IM, (c / IM) % IM, DIM == 3 ? c / (IM * IM) : 0};
+#pragma unroll
+            for (int d = 0; d < DIM; ++d) W *= IM == 2 ? (o[d] ? tt[d] : 1.0 - tt[d]) : lw[d][o[d]];
             double v[DIM + 2];
             if (boxed) {
                 int u[3] = {0, 0, 0};
-                for (int d = 0; d < DIM; ++d) u[d] = rec.b[d] + o[d] - bo[d];
+                for (int d = 0; d < DIM; ++d) u[d] = rec.b[d] + o[d] - LO - bo[d];
                 const int lin = (u[2] * bs[1] + u[1]) * bs[0] + u[0];
                 const int k = woff[lin >> 5] + __popc(bits[lin >> 5] & ((1u << (lin & 31)) - 1u));
 #pragma unroll
                 for (int q = 0; q < DIM + 2; ++q) v[q] = (double)mom[q][k];
             } else {
                 int ix[3] = {0, 0, 0};
-                for (int d = 0; d < DIM; ++d) ix[d] = clamp_or_wrap(rec.b[d] + o[d], nn[d], a.lb.per[d]);
+                for (int d = 0; d < DIM; ++d) ix[d] = clamp_or_wrap(rec.b[d] + o[d] - LO, nn[d], a.lb.per[d]);
                 T f[L::Q];
                 C g[L::QG];
                 pull<DIM, SF, T, C>(a.lb, ix[0], ix[1], ix[2], f, g);

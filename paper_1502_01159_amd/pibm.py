@@ -45,6 +45,7 @@ class Params(ctypes.Structure):
         ("gravity", ctypes.c_double), ("kappa_T", ctypes.c_double), ("E_star", ctypes.c_double),
         ("poisson", ctypes.c_double), ("mu_fric", ctypes.c_double), ("n_sub", ctypes.c_int),
         ("beta_p", ctypes.c_double), ("c_r", ctypes.c_double), ("skin", ctypes.c_double),
+        ("interp_order", ctypes.c_int),
     ]
 
 
@@ -150,6 +151,7 @@ def make_params(cfg: dict, storage: str = "f32") -> Params:
     p.beta_p = float(cfg.get("beta_p", 0.0))
     p.c_r = float(cfg.get("c_r", 1.0))
     p.skin = float(cfg.get("skin", 1.0))
+    p.interp_order = int(cfg.get("interp_order", 2))
     return p
 
 

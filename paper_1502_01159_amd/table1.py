@@ -35,10 +35,12 @@ def nusselt(sim) -> float:
 
 
 def run_case(pibm, n: int, Ra: float, Ar: float, storage: str = "f32", chunk: int = 5000, tol: float = 1e-4,
-             max_steps: int = 600000, log=None):
+             max_steps: int = 600000, log=None, **overrides):
     """Steps until Nu changes by less than tol (relative) over two consecutive
-    chunks, or max_steps.  Returns (Nu, steps, converged, seconds)."""
+    chunks, or max_steps.  `overrides` replace parameters of the case (e.g.
+    interp_order, marker_mode).  Returns (Nu, steps, converged, seconds)."""
     cfg, P = W.annulus_2d(n=n, Ra=Ra, Ar=Ar)
+    cfg = W.with_overrides(cfg, **overrides)
     sim = pibm.Simulation(cfg, P, storage=storage)
     t0 = time.perf_counter()
     hist = []
@@ -67,6 +69,8 @@ def main(argv=None) -> int:
     ap.add_argument("--chunk", type=int, default=5000)
     ap.add_argument("--tol", type=float, default=1e-4)
     ap.add_argument("--max-steps", type=int, default=600000)
+    ap.add_argument("--interp-order", type=int, default=2, help="Lagrange nodes per axis, Eq. (lbm6): 2 or 4")
+    ap.add_argument("--marker-mode", type=int, default=1, help="0 surface elements, 1 the paper's pi s^2 / 4")
     args = ap.parse_args(argv)
     from . import pibm
 
@@ -75,9 +79,11 @@ def main(argv=None) -> int:
     log = lambda m: print(m, flush=True)
     rows = []
     for Ra, Ar in cases:
-        nu, steps, ok, sec = run_case(pibm, args.n, Ra, Ar, args.storage, args.chunk, args.tol, args.max_steps, log)
+        nu, steps, ok, sec = run_case(pibm, args.n, Ra, Ar, args.storage, args.chunk, args.tol, args.max_steps, log,
+                                      interp_order=args.interp_order, marker_mode=args.marker_mode)
         ref = PRINTED.get((Ra, Ar))
-        row = dict(Ra=Ra, Ar=Ar, n=args.n, Nu=round(nu, 4), printed=ref,
+        row = dict(Ra=Ra, Ar=Ar, n=args.n, interp_order=args.interp_order, marker_mode=args.marker_mode,
+                   Nu=round(nu, 4), printed=ref,
                    rel_err=None if ref is None else round(nu / ref - 1.0, 4), steps=steps, converged=ok,
                    seconds=round(sec, 1))
         rows.append(row)

@@ -82,18 +82,20 @@ def _box_particles(dim, n, seed):
     return np.array(rows)
 
 
+@pytest.mark.parametrize("order", [2, 4])
 @pytest.mark.parametrize("dim", [2, 3])
-def test_single_step_random_state_f64(gpu, oracle_mod, dim):
+def test_single_step_random_state_f64(gpu, oracle_mod, dim, order):
     """One step from a random non-equilibrium state on a ragged multi-tile
     box (x periodic, y and z walls): every population, and every particle's
-    reactions and new state, agree with the oracle."""
+    reactions and new state, agree with the oracle; with the multilinear
+    (i_max = 2) and the cubic (i_max = 4) interpolation of Eq. (lbm6)."""
     if dim == 2:
         cfg = dict(dim=2, nx=150, ny=37, nz=1, periodic=[1, 0, 0])
     else:
         cfg = dict(dim=3, nx=70, ny=11, nz=10, periodic=[1, 0, 0])
     cfg.update(T_wall=[0.2, 0.7, 0.0, 1.0, 0.3, 0.6], T_init=0.4, T_ref=0.35, Ra=0.0, nu=0.05, Pr=0.7,
                Gr=300.0, Lc=8.0, gravity=2e-3, kappa_T=1.0, marker_mode=1, marker_spacing=1.0,
-               E_star=50.0, poisson=0.33, mu_fric=0.3, n_sub=3, beta_p=0.05, c_r=1.0)
+               E_star=50.0, poisson=0.33, mu_fric=0.3, n_sub=3, beta_p=0.05, c_r=1.0, interp_order=order)
     P = _box_particles(dim, cfg["nx"], 7)
     P[0, 12] = W.THERMO
     sim = gpu.Simulation(cfg, P, storage="f64")

@@ -259,6 +259,59 @@ def test_interpolation_exact_for_linear_fields(oracle_mod, dim):
     assert got[6] == pytest.approx(expect_H, rel=1e-12)
 
 
+@pytest.mark.parametrize("dim", [2, 3])
+def test_interpolation_exact_for_cubic_fields_order4(oracle_mod, dim):
+    """Eq. (lbm6) with i_max = 4: the tensor-product cubic Lagrange interpolant
+    through nodes b - 1 .. b + 2 reproduces fields cubic in each coordinate
+    (mixed terms included) exactly; the i_max = 2 interpolant of the same
+    fields does not.  Moments are set as in the linear pin."""
+    n = 24
+    mk = base2d if dim == 2 else base3d
+    U = np.array([0.01, -0.02, 0.015 if dim == 3 else 0.0])
+    Om = np.array([0.0, 0.0, 0.003]) if dim == 2 else np.array([0.002, -0.001, 0.003])
+    c = (11.3, 12.1, 11.7 if dim == 3 else 0.0)
+    P = np.array([prow(c, 4.0, T=0.8, flags=W.FIXED, u=U, om=Om)])
+    rho_c = lambda X, Y, Z: 1.0 + 0.01 * X - 2e-4 * Y * Y + 1e-6 * X ** 3 + 3e-7 * X * Y * Z + 2e-8 * (X * Y) ** 3
+    jx_c = lambda X, Y, Z: 0.002 + 1e-4 * X * Y - 2e-6 * Y ** 3 + 5e-7 * Z ** 3 + 1e-8 * X ** 3 * Z ** 2
+    s_c = lambda X, Y, Z: 0.1 + 0.02 * X + 3e-4 * Z * Z - 1e-6 * X * Y * Y + 4e-7 * Z ** 3
+
+    def run(order):
+        cfg = mk(nx=n, ny=n, nz=n, periodic=[1, 1, 1], interp_order=order)
+        o = oracle_mod.Oracle(cfg, P)
+        ii = np.indices(o.shape)                   # (z, y, x)
+        x, y, z = ii[2].ravel().astype(float), ii[1].ravel().astype(float), ii[0].ravel().astype(float)
+        if dim == 2:
+            z = np.zeros_like(z)
+        f = np.zeros((o.Q, o.N))
+        g = np.zeros((o.Qg, o.N))
+        f[1] = jx_c(x + 1.0, y, z)                 # streamed: j_x(x) = jx_c(x)
+        f[0] = rho_c(x, y, z) - jx_c(x, y, z)
+        g[0] = s_c(x, y, z)
+        o.set_populations(f, g)
+        o.step(1)
+        m = o.markers(0)
+        r, A = m[:, :3], m[:, 3]
+        X = np.array(c) + r
+        if dim == 2:
+            X[:, 2] = 0.0
+        Ul = U + np.cross(Om, r)
+        if dim == 2:
+            Ul[:, 2] = 0.0
+        rl = rho_c(X[:, 0], X[:, 1], X[:, 2])
+        jl = np.zeros_like(X)
+        jl[:, 0] = jx_c(X[:, 0], X[:, 1], X[:, 2])
+        expect_F = -((2.0 * (rl[:, None] * Ul - jl)) * A[:, None]).sum(0)
+        expect_H = (2.0 * (0.8 - s_c(X[:, 0], X[:, 1], X[:, 2])) * A).sum()
+        got = o.reactions()[0]
+        return got, expect_F, expect_H
+
+    got, eF, eH = run(4)
+    assert np.allclose(got[:3], eF, rtol=1e-11, atol=1e-13)
+    assert got[6] == pytest.approx(eH, rel=1e-11)
+    got2, eF2, eH2 = run(2)
+    assert abs(got2[6] - eH2) > 1e-6 * abs(eH2)
+
+
 def test_markers_geometry(oracle_mod):
     """Lagrangian points lie on the body surface; the 2D ring has round(pi D)
     points with weights pi D / N, the sphere round(pi D^2) points with weights
