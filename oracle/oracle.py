@@ -38,7 +38,7 @@ class OrcParams(ctypes.Structure):
         ("n_sub", ctypes.c_int),
         ("beta_p", ctypes.c_double), ("c_r", ctypes.c_double),
         ("marker_mode", ctypes.c_int), ("marker_spacing", ctypes.c_double),
-        ("interp_order", ctypes.c_int),
+        ("interp_order", ctypes.c_int), ("lattice", ctypes.c_int),
     ]
 
 
@@ -144,6 +144,7 @@ def make_params(cfg: dict) -> OrcParams:
     p.c_r = cfg.get("c_r", 1.0)
     p.marker_mode = int(cfg.get("marker_mode", 0))
     p.interp_order = int(cfg.get("interp_order", 2))
+    p.lattice = int(cfg.get("lattice", 19))
     p.marker_spacing = cfg.get("marker_spacing", 1.0)
     return p
 
@@ -167,7 +168,7 @@ class Oracle:
         self.dim = self.params.dim
         self.shape = (self.params.nz, self.params.ny, self.params.nx)
         self.N = int(L.orc_num_nodes(self._h))
-        self.Q = 9 if self.dim == 2 else 19
+        self.Q = 9 if self.dim == 2 else (15 if int(cfg.get("lattice", 19)) == 15 else 19)
         self.Qg = 5 if self.dim == 2 else 7
 
     def __del__(self):

@@ -62,6 +62,7 @@ typedef struct {
     int marker_mode;         /* 0 surface element, 1 A = pi s^2/4, 2 one point */
     double marker_spacing;
     int interp_order;        /* Lagrange nodes per axis in Eq. (lbm6): 2 (0 means 2) or 4 */
+    int lattice;             /* 3D flow velocity set: 19 (0 means 19) or 15 (Sec. 2.1's D3Q15) */
 } orc_params;
 
 enum { ORC_FIXED = 1, ORC_THERMO = 2 };
@@ -103,9 +104,9 @@ typedef struct {
 } orc_state;
 
 /* ------------------------------------------------------------------------ */
-/* Lattices.  D2Q9 / D3Q19 for the flow (Sec. 2.1 gives the D3Q15 form of   */
-/* the same BGK scheme), D2Q5 / D3Q7 for temperature (reading: linear        */
-/* equilibrium, c_sg^2 = 1/3 in 2D and 1/4 in 3D).                           */
+/* Lattices.  D2Q9 / D3Q19 for the flow, or the D3Q15 of Sec. 2.1 (rest,    */
+/* six faces, eight corners; w = 2/9, 1/9, 1/72); D2Q5 / D3Q7 for           */
+/* temperature (reading: linear equilibrium, c_sg^2 = 1/3 in 2D, 1/4 in 3D). */
 /* ------------------------------------------------------------------------ */
 static void set_lattice(orc_state *s)
 {
@@ -114,6 +115,9 @@ static void set_lattice(orc_state *s)
         {0,0,0},{1,0,0},{-1,0,0},{0,1,0},{0,-1,0},{0,0,1},{0,0,-1},
         {1,1,0},{-1,-1,0},{1,-1,0},{-1,1,0},{1,0,1},{-1,0,-1},{1,0,-1},{-1,0,1},
         {0,1,1},{0,-1,-1},{0,1,-1},{0,-1,1}};
+    static const int d3q15[15][3] = {
+        {0,0,0},{1,0,0},{-1,0,0},{0,1,0},{0,-1,0},{0,0,1},{0,0,-1},
+        {1,1,1},{-1,-1,-1},{1,1,-1},{-1,-1,1},{1,-1,1},{-1,1,-1},{-1,1,1},{1,-1,-1}};
     memset(s->e, 0, sizeof s->e);
     memset(s->eg, 0, sizeof s->eg);
     if (s->p.dim == 2) {
@@ -128,6 +132,18 @@ static void set_lattice(orc_state *s)
             s->wg[a] = a == 0 ? 1.0/3.0 : 1.0/6.0;
         }
         s->csg2 = 1.0/3.0;
+    } else if (s->p.lattice == 15) {
+        s->Q = 15; s->Qg = 7;
+        for (int a = 0; a < 15; a++) {
+            for (int d = 0; d < 3; d++) s->e[a][d] = d3q15[a][d];
+            int n2 = s->e[a][0]*s->e[a][0] + s->e[a][1]*s->e[a][1] + s->e[a][2]*s->e[a][2];
+            s->w[a] = n2 == 0 ? 2.0/9.0 : (n2 == 1 ? 1.0/9.0 : 1.0/72.0);
+        }
+        for (int a = 0; a < 7; a++) {
+            for (int d = 0; d < 3; d++) s->eg[a][d] = d3q19[a][d];
+            s->wg[a] = a == 0 ? 1.0/4.0 : 1.0/8.0;
+        }
+        s->csg2 = 1.0/4.0;
     } else {
         s->Q = 19; s->Qg = 7;
         for (int a = 0; a < 19; a++) {

@@ -152,6 +152,47 @@ def test_poiseuille_magic_tau_exact(oracle_mod, dim):
     assert np.max(np.abs(u[..., 0])) < 1e-13
 
 
+def test_d3q15_poiseuille_magic_tau_exact(oracle_mod):
+    """P5 on the D3Q15 lattice of Sec. 2.1 (w = 2/9, 1/9, 1/72): the body-force
+    channel between halfway bounce-back walls is exact to round-off at the
+    magic tau, which needs the weights' second and fourth moments right."""
+    H = 11
+    tau = 0.5 + math.sqrt(3.0) / 4.0
+    F = 1e-5
+    cfg = base3d(nx=H, ny=2, nz=2, periodic=[0, 1, 1], T_wall=[1.0] * 6, T_init=1.0, T_ref=0.0,
+                 tau_f=tau, tau_g=0.8, gbeta=F, lattice=15)
+    o = oracle_mod.Oracle(cfg)
+    assert o.Q == 15
+    o.step(9000)
+    rho, u, T = o.fields()
+    nu = (tau - 0.5) / 3.0
+    x = np.arange(H)
+    exact = F * (x + 0.5) * (H - 0.5 - x) / (2 * nu)
+    assert np.max(np.abs(u[0, 0, :, 2] - exact)) / exact.max() < 1e-10
+    assert np.max(np.abs(u[..., 0])) < 1e-13
+
+
+def test_d3q15_momentum_conserved_fluid_plus_particles(oracle_mod):
+    """P3 on D3Q15: sum j + sum m U is invariant with moving, colliding
+    particles in a periodic box."""
+    cfg = base3d(nx=24, ny=20, nz=22, E_star=50.0, n_sub=3, mu_fric=0.3, lattice=15)
+    P = np.array([prow((6.0, 9.0, 10.0), 3.0, 2.5, u=(0.02, 0.0, 0.005), om=(0, 0.01, 0)),
+                  prow((12.3, 9.4, 10.5), 3.0, 3.0, u=(-0.02, 0.001, 0.0))])
+    o = oracle_mod.Oracle(cfg, P)
+
+    def total():
+        t = o.totals()
+        q = o.particles()
+        m = q[:, 13] * 4.0 / 3.0 * math.pi * q[:, 12] ** 3
+        return t[1:4] + (m[:, None] * q[:, 3:6]).sum(0)
+
+    p0 = total()
+    m0 = o.totals()[0]
+    o.step(40)
+    assert np.max(np.abs(total() - p0)) < 1e-11
+    assert abs(o.totals()[0] - m0) < 1e-13 * m0
+
+
 def test_poiseuille_second_order_off_magic(oracle_mod):
     """P5 (other tau): the error of the halfway-wall parabola falls ~4x when
     the channel doubles (second order)."""
