@@ -216,8 +216,9 @@ def main() -> int:
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--workload", default="c3", choices=sorted(WORKLOAD_TEXT))
     ap.add_argument("--storage", default="f32", choices=sorted(STORAGE_BYTES))
-    ap.add_argument("--variants", default="f16,bf16,mlp",
-                    help="extra storage formats timed beside the main one, and 'mlp' for the learned part")
+    ap.add_argument("--variants", default="f16,bf16,q15,mlp",
+                    help="extra storage formats timed beside the main one, 'q15' for the D3Q15 flow lattice "
+                         "(FP32, 3D workloads) and 'mlp' for the learned part")
     ap.add_argument("--cpu-steps", type=int, default=2)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--empty", action="store_true", help="analysis: the same lattice without particles")
@@ -248,10 +249,13 @@ def main() -> int:
 
     variants = {}
     for st in [s for s in args.variants.split(",") if s and s != args.storage and s != "mlp"]:
-        r = time_gpu(cfg, P, st, max(args.steps // 2, 10), args.warmup, profile=True)
+        if st == "q15" and cfg["dim"] != 3:
+            continue
+        vcfg, vst = (W.with_overrides(cfg, lattice=15), "f32") if st == "q15" else (cfg, st)
+        r = time_gpu(vcfg, P, vst, max(args.steps // 2, 10), args.warmup, profile=True)
         lms, ln = r["prof"]["lattice"]
         n_steps = max(args.steps // 2, 10)
-        b = 2 * (Q + Qg) * STORAGE_BYTES[st]
+        b = 2 * (r["Q"] + r["Qg"]) * STORAGE_BYTES[vst]
         variants[st] = dict(value=round(N * n_steps / (r["ms"] * 1e-3) / 1e6, 1), unit="MLUPS",
                             ms_per_step=round(r["ms"] / n_steps, 4),
                             lattice_kernel_ms=round(lms / max(ln, 1), 4),

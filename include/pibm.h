@@ -68,7 +68,7 @@ typedef enum { PIBM_MARKERS_SURFACE = 0, PIBM_MARKERS_PAPER = 1, PIBM_MARKERS_PO
 /* Problem statement (Sec. 2): lattice, walls, Ra/Pr or nu/Gr, particles'
  * material.  Fields are read once by pibm_init. */
 typedef struct pibm_params {
-    int dim;                 /* 2 (D2Q9 + D2Q5) or 3 (D3Q19 + D3Q7) */
+    int dim;                 /* 2 (D2Q9 + D2Q5) or 3 (D3Q19 or D3Q15, see lattice, + D3Q7) */
     int nx, ny, nz;          /* nodes per axis; nz = 1 in 2D */
     int periodic[3];         /* non-zero: periodic axis; zero: two walls */
     int storage;             /* pibm_storage */
@@ -101,6 +101,11 @@ typedef struct pibm_params {
     int interp_order;        /* Lagrange nodes per axis of the interpolation, Eq. (lbm6): 2 (the
                                 cell's corners, multilinear; 0 means 2) or 4 (nodes floor(X) - 1 ..
                                 floor(X) + 2, cubic); other values are PIBM_EINVAL */
+    int lattice;             /* 3D flow velocity set: 19 (D3Q19; 0 means 19) or 15 (the D3Q15 of
+                                Sec. 2.1: rest, faces, corners, w = 2/9, 1/9, 1/72; FP32 and FP64
+                                storage only); populations are ordered rest, +-x, +-y, +-z, then
+                                the corners (+,+,+) (-,-,-) (+,+,-) (-,-,+) (+,-,+) (-,+,-)
+                                (-,+,+) (+,-,-) */
 } pibm_params;
 
 enum { PIBM_FIXED = 1, PIBM_THERMO = 2 };

@@ -166,6 +166,10 @@ int check_params(const pibm_params *p)
     if (p->marker_mode < 0 || p->marker_mode > 2) return PIBM_EINVAL;
     if (p->n_sub < 1) return PIBM_EINVAL;
     if (p->interp_order != 0 && p->interp_order != 2 && p->interp_order != 4) return PIBM_EINVAL;
+    if (p->lattice != 0 && p->lattice != 19 && p->lattice != 15) return PIBM_EINVAL;
+    // D3Q15 is a 3D flow lattice, built for the FP32 and FP64 storage
+    if (p->lattice == 15 && (p->dim != 3 || (p->storage != PIBM_STORE_F32 && p->storage != PIBM_STORE_F64)))
+        return PIBM_EINVAL;
     const Derived d = derive(*p);
     if (!(d.tau_f > 0.5) || !(d.tau_g > 0.5)) return PIBM_EINVAL;
     if (!std::isfinite(d.gbeta)) return PIBM_EINVAL;
@@ -178,7 +182,7 @@ int make_plan(const pibm_params *p, const pibm_particle *pt, int np, Plan &P)
     if (st) return st;
     if (np < 0 || (np > 0 && !pt)) return PIBM_EINVAL;
     P.dim = p->dim;
-    P.Q = p->dim == 2 ? 9 : 19;
+    P.Q = p->dim == 2 ? 9 : (p->lattice == 15 ? 15 : 19);
     P.QG = p->dim == 2 ? 5 : 7;
     P.N = (long long)p->nx * p->ny * p->nz;
     P.ssize = p->storage == PIBM_STORE_F64 ? 8 : (p->storage == PIBM_STORE_F32 ? 4 : 2);
@@ -708,8 +712,12 @@ int dispatch(pibm_ctx *c, A... args)
 {
     const bool d3 = c->p.dim == 3;
     switch (c->p.storage) {
-    case PIBM_STORE_F32: return d3 ? F<3, StF32>::run(c, args...) : F<2, StF32>::run(c, args...);
-    case PIBM_STORE_F64: return d3 ? F<3, StF64>::run(c, args...) : F<2, StF64>::run(c, args...);
+    case PIBM_STORE_F32:
+        if (d3 && c->p.lattice == 15) return F<3, OnQ15<StF32>>::run(c, args...);
+        return d3 ? F<3, StF32>::run(c, args...) : F<2, StF32>::run(c, args...);
+    case PIBM_STORE_F64:
+        if (d3 && c->p.lattice == 15) return F<3, OnQ15<StF64>>::run(c, args...);
+        return d3 ? F<3, StF64>::run(c, args...) : F<2, StF64>::run(c, args...);
     case PIBM_STORE_F16DEV: return d3 ? F<3, StF16>::run(c, args...) : F<2, StF16>::run(c, args...);
     default: return d3 ? F<3, StBF16>::run(c, args...) : F<2, StBF16>::run(c, args...);
     }
@@ -775,7 +783,10 @@ void dev_to_stored(const pibm_ctx *c, char *buf, size_t i, double v, double w)
     }
 }
 
-double wf(int dim, int q) { return dim == 2 ? Lat<2>::w(q) : Lat<3>::w(q); }
+double wf(int dim, int lattice, int q)
+{
+    return dim == 2 ? Lat<2>::w(q) : (lattice == 15 ? LatT<3, 15>::w(q) : Lat<3>::w(q));
+}
 double wgt(int dim, int q) { return dim == 2 ? Lat<2>::wg(q) : Lat<3>::wg(q); }
 
 DevParticle to_dev(const pibm_particle &q, int tmpl)
@@ -1008,7 +1019,7 @@ int pibm_get_populations(pibm_ctx *c, double *f, double *g)
     const int st = sync_impl(c);
     if (c->device_lost) return PIBM_EDEVICE;
     for (int q = 0; q < Q; ++q)
-        for (size_t n = 0; n < N; ++n) f[q * N + n] = wf(dim, q) + stored_to_dev(c, hf.data(), q * Ns + n, wf(dim, q));
+        for (size_t n = 0; n < N; ++n) f[q * N + n] = wf(dim, c->p.lattice, q) + stored_to_dev(c, hf.data(), q * Ns + n, wf(dim, c->p.lattice, q));
     for (int q = 0; q < QG; ++q)
         for (size_t n = 0; n < N; ++n)
             g[q * N + n] = wgt(dim, q) * c->p.T_ref + stored_to_dev(c, hg.data(), q * Ns + n, wgt(dim, q));
@@ -1023,7 +1034,7 @@ int pibm_set_populations(pibm_ctx *c, const double *f, const double *g)
     const size_t Ns = (size_t)c->P.Ns, N = (size_t)c->P.N, ss = c->P.ssize;
     std::vector<char> hf(Q * Ns * ss, 0), hg(QG * Ns * ss, 0);
     for (int q = 0; q < Q; ++q)
-        for (size_t n = 0; n < N; ++n) dev_to_stored(c, hf.data(), q * Ns + n, f[q * N + n] - wf(dim, q), wf(dim, q));
+        for (size_t n = 0; n < N; ++n) dev_to_stored(c, hf.data(), q * Ns + n, f[q * N + n] - wf(dim, c->p.lattice, q), wf(dim, c->p.lattice, q));
     for (int q = 0; q < QG; ++q)
         for (size_t n = 0; n < N; ++n)
             dev_to_stored(c, hg.data(), q * Ns + n, g[q * N + n] - wgt(dim, q) * c->p.T_ref, wgt(dim, q));

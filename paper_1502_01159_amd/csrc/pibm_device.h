@@ -24,12 +24,12 @@
 namespace pibm {
 
 // --------------------------------------------------------------------------
-// Lattices.  Flow: D2Q9 / D3Q19 BGK.  Temperature: D2Q5 / D3Q7 with a linear
-// equilibrium, c_sg^2 = 1/3 (D2Q5) and 1/4 (D3Q7).
+// Lattices.  Flow: D2Q9 / D3Q19 BGK, or the D3Q15 of Sec. 2.1.  Temperature:
+// D2Q5 / D3Q7 with a linear equilibrium, c_sg^2 = 1/3 (D2Q5) and 1/4 (D3Q7).
 // --------------------------------------------------------------------------
-template <int DIM> struct Lat;
+template <int DIM, int QF> struct LatT;
 
-template <> struct Lat<2> {
+template <> struct LatT<2, 9> {
     static constexpr int Q = 9, QG = 5;
     __host__ __device__ static constexpr int e(int q, int d) {
         // rest, +x, +y, -x, -y, (+x+y), (-x+y), (-x-y), (+x-y)
@@ -45,7 +45,7 @@ template <> struct Lat<2> {
     static constexpr double csg2_inv = 3.0;
 };
 
-template <> struct Lat<3> {
+template <> struct LatT<3, 19> {
     static constexpr int Q = 19, QG = 7;
     // rest; +-x, +-y, +-z; then the 12 edge directions in opposite pairs
     __host__ __device__ static constexpr int e(int q, int d) {
@@ -61,6 +61,54 @@ template <> struct Lat<3> {
     __host__ __device__ static constexpr double wg(int q) { return q == 0 ? 0.25 : 0.125; }
     static constexpr double csg2_inv = 4.0;
 };
+
+// D3Q15 (Sec. 2.1): rest; +-x, +-y, +-z; then the 8 corners in opposite pairs
+// (+,+,+) (-,-,-) (+,+,-) (-,-,+) (+,-,+) (-,+,-) (-,+,+) (+,-,-);
+// w = 2/9, 1/9, 1/72.  Same thermal lattice (D3Q7).
+template <> struct LatT<3, 15> {
+    static constexpr int Q = 15, QG = 7;
+    __host__ __device__ static constexpr int e(int q, int d) {
+        return q == 0 ? 0
+             : q < 7 ? ((q - 1) / 2 == d ? ((q & 1) ? 1 : -1) : 0)
+                     : (d == 0 ? (q == 7 || q == 9 || q == 11 || q == 14 ? 1 : -1)
+                        : d == 1 ? (q == 7 || q == 9 || q == 12 || q == 13 ? 1 : -1)
+                                 : (q == 7 || q == 10 || q == 11 || q == 13 ? 1 : -1));
+    }
+    __host__ __device__ static constexpr int opp(int q) { return q == 0 ? 0 : ((q & 1) ? q + 1 : q - 1); }
+    __host__ __device__ static constexpr double w(int q) { return q == 0 ? 2.0 / 9.0 : (q < 7 ? 1.0 / 9.0 : 1.0 / 72.0); }
+    __host__ __device__ static constexpr double wg(int q) { return q == 0 ? 0.25 : 0.125; }
+    static constexpr double csg2_inv = 4.0;
+};
+
+template <int DIM> using Lat = LatT<DIM, DIM == 2 ? 9 : 19>;
+
+// Lattice facts checked at compile time: opposite directions, unit weight
+// sum, second moment c_s^2 = 1/3 and isotropic fourth moment (1/9 for xxyy,
+// 1/3 for xxxx).
+template <class L> constexpr bool lattice_ok()
+{
+    double w0 = 0, wxx = 0, wxy = 0, wxxyy = 0, wxxxx = 0;
+    for (int q = 0; q < L::Q; ++q) {
+        for (int d = 0; d < 3; ++d)
+            if (L::e(L::opp(q), d) != -L::e(q, d)) return false;
+        const double ex = L::e(q, 0), ey = L::e(q, 1);
+        w0 += L::w(q); wxx += L::w(q) * ex * ex; wxy += L::w(q) * ex * ey;
+        wxxyy += L::w(q) * ex * ex * ey * ey; wxxxx += L::w(q) * ex * ex * ex * ex;
+    }
+    auto near = [](double a, double b) { return a - b < 1e-15 && b - a < 1e-15; };
+    return near(w0, 1.0) && near(wxx, 1.0 / 3.0) && near(wxy, 0.0) && near(wxxyy, 1.0 / 9.0) && near(wxxxx, 1.0 / 3.0);
+}
+static_assert(lattice_ok<LatT<2, 9>>(), "D2Q9 table");
+static_assert(lattice_ok<LatT<3, 19>>(), "D3Q19 table");
+static_assert(lattice_ok<LatT<3, 15>>(), "D3Q15 table");
+
+// The flow lattice of a kernel instance travels with its storage traits: a
+// traits class with QF = 15 selects D3Q15, any other the default lattice.
+template <class Base> struct OnQ15 : Base { static constexpr int QF = 15; };
+template <class SF, class = void> struct FlowQ { static constexpr int value = 0; };
+template <class SF> struct FlowQ<SF, decltype((void)SF::QF)> { static constexpr int value = SF::QF; };
+template <int DIM, class SF>
+using LatOf = LatT<DIM, DIM == 3 && FlowQ<SF>::value == 15 ? 15 : (DIM == 2 ? 9 : 19)>;
 
 // --------------------------------------------------------------------------
 // Counter-based uniform numbers for stochastic rounding: a 32-bit integer
@@ -268,7 +316,7 @@ __device__ __forceinline__ S *addr_at(S *base, uint32_t elem)
 template <int DIM, class SF, class T, class TG>
 __device__ __forceinline__ void pull(const LbmArgs<T> &a, int x, int y, int z, T *f, TG *g)
 {
-    using L = Lat<DIM>;
+    using L = LatOf<DIM, SF>;
     using S = typename SF::S;
     const S *fa = (const S *)a.fA;
     const S *ga = (const S *)a.gA;
@@ -319,10 +367,9 @@ __device__ __forceinline__ void pull(const LbmArgs<T> &a, int x, int y, int z, T
 }
 
 // Raw moments of the streamed deviations: rho - 1, j, S - T_ref.
-template <int DIM, class C, class T>
+template <int DIM, class L, class C, class T>
 __device__ __forceinline__ void moments(const T *f, const C *g, C &drho, C *j, C &dS)
 {
-    using L = Lat<DIM>;
     drho = 0; j[0] = 0; j[1] = 0; j[2] = 0; dS = 0;
 #pragma unroll
     for (int q = 0; q < L::Q; ++q) {
@@ -443,7 +490,7 @@ template <int DIM, class SF, bool MACRO>
 __global__ __launch_bounds__(LBM_THREADS) void k_lbm(LbmArgs<typename SF::T> a)
 {
     using T = typename SF::T;
-    using L = Lat<DIM>;
+    using L = LatOf<DIM, SF>;
     using TL = Tile<DIM>;
     constexpr int NC = DIM + 1;
     constexpr int RMAX = DIM == 3 ? 16 : 4;          // footprint rows per point
@@ -837,7 +884,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k
 {
     using T = typename SF::T;
     using C = typename SF::C;
-    using L = Lat<DIM>;
+    using L = LatOf<DIM, SF>;
     constexpr int MAXSHELL = K2Shell<T>::MAX;
     __shared__ double wred[4][8];
     __shared__ int spart[256];
@@ -933,7 +980,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k
                 C g[L::QG];
                 pull<DIM, SF, T, C>(a.lb, ix[0], ix[1], ix[2], f, g);
                 C drho, j[3], dS;
-                moments<DIM, C>(f, g, drho, j, dS);
+                moments<DIM, L, C>(f, g, drho, j, dS);
                 mom[0][k] = (T)drho;
 #pragma unroll
                 for (int d = 0; d < DIM; ++d) mom[1 + d][k] = (T)j[d];
@@ -980,7 +1027,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k
                 C g[L::QG];
                 pull<DIM, SF, T, C>(a.lb, ix[0], ix[1], ix[2], f, g);
                 C drho, j[3], dS;
-                moments<DIM, C>(f, g, drho, j, dS);
+                moments<DIM, L, C>(f, g, drho, j, dS);
                 v[0] = (double)drho;
 #pragma unroll
                 for (int d = 0; d < DIM; ++d) v[1 + d] = (double)j[d];
@@ -1110,7 +1157,7 @@ __global__ __launch_bounds__(FEAT_THREADS) void k_features(FeatArgs<typename SF:
 {
     using T = typename SF::T;
     using C = double;
-    using L = Lat<DIM>;
+    using L = LatOf<DIM, SF>;
     constexpr int NN = DIM == 3 ? 4 : 6;
     // waves 0 .. MW - 1 sum the shell's moments while wave MW finds the
     // neighbours; the two chains of loads overlap and meet at one barrier
@@ -1159,7 +1206,7 @@ __global__ __launch_bounds__(FEAT_THREADS) void k_features(FeatArgs<typename SF:
             C g[L::QG];
             pull<DIM, SF, T, C>(a.lb, c[0], c[1], c[2], f, g);
             C drho, j[3], dS;
-            moments<DIM, C>(f, g, drho, j, dS);
+            moments<DIM, L, C>(f, g, drho, j, dS);
             sm[0] += 1.0 + drho; sm[1] += j[0]; sm[2] += j[1]; sm[3] += j[2]; sm[4] += dS;
             cnt += 1.0;
         }

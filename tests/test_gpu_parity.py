@@ -82,27 +82,29 @@ def _box_particles(dim, n, seed):
     return np.array(rows)
 
 
-@pytest.mark.parametrize("order", [2, 4])
-@pytest.mark.parametrize("dim", [2, 3])
-def test_single_step_random_state_f64(gpu, oracle_mod, dim, order):
+@pytest.mark.parametrize("dim,order,lattice", [(2, 2, 19), (3, 2, 19), (2, 4, 19), (3, 4, 19), (3, 2, 15)])
+def test_single_step_random_state_f64(gpu, oracle_mod, dim, order, lattice):
     """One step from a random non-equilibrium state on a ragged multi-tile
     box (x periodic, y and z walls): every population, and every particle's
     reactions and new state, agree with the oracle; with the multilinear
-    (i_max = 2) and the cubic (i_max = 4) interpolation of Eq. (lbm6)."""
+    (i_max = 2) and the cubic (i_max = 4) interpolation of Eq. (lbm6), and on
+    the D3Q15 flow lattice of Sec. 2.1."""
     if dim == 2:
         cfg = dict(dim=2, nx=150, ny=37, nz=1, periodic=[1, 0, 0])
     else:
         cfg = dict(dim=3, nx=70, ny=11, nz=10, periodic=[1, 0, 0])
     cfg.update(T_wall=[0.2, 0.7, 0.0, 1.0, 0.3, 0.6], T_init=0.4, T_ref=0.35, Ra=0.0, nu=0.05, Pr=0.7,
                Gr=300.0, Lc=8.0, gravity=2e-3, kappa_T=1.0, marker_mode=1, marker_spacing=1.0,
-               E_star=50.0, poisson=0.33, mu_fric=0.3, n_sub=3, beta_p=0.05, c_r=1.0, interp_order=order)
+               E_star=50.0, poisson=0.33, mu_fric=0.3, n_sub=3, beta_p=0.05, c_r=1.0, interp_order=order,
+               lattice=lattice)
     P = _box_particles(dim, cfg["nx"], 7)
     P[0, 12] = W.THERMO
     sim = gpu.Simulation(cfg, P, storage="f64")
     ref = oracle_mod.Oracle(cfg, P)
     Q, Qg = sim.Q, sim.Qg
     w = np.array([4 / 9] + [1 / 9] * 4 + [1 / 36] * 4) if dim == 2 else \
-        np.array([1 / 3] + [1 / 18] * 6 + [1 / 36] * 12)
+        (np.array([2 / 9] + [1 / 9] * 6 + [1 / 72] * 8) if lattice == 15 else
+         np.array([1 / 3] + [1 / 18] * 6 + [1 / 36] * 12))
     wg = np.array([1 / 3] + [1 / 6] * 4) if dim == 2 else np.array([1 / 4] + [1 / 8] * 6)
     f0 = W.perturbed_populations(11, Q, sim.N, w, 1.0, 0.05)
     g0 = W.perturbed_populations(12, Qg, sim.N, wg, 0.5, 0.2)
@@ -124,9 +126,18 @@ def test_single_step_random_state_f64(gpu, oracle_mod, dim, order):
     assert np.allclose(q[:, 14], rq[:, 14], rtol=1e-12, atol=1e-14)
 
 
-@pytest.mark.parametrize("name,steps", [("c1", 300), ("c2_small", 200), ("c3_small", 60), ("c4_small", 60)])
+def workload_case(name):
+    """A named workload; the suffix _q15 puts it on the D3Q15 flow lattice."""
+    if name.endswith("_q15"):
+        cfg, P = W.workload(name[:-4])
+        return W.with_overrides(cfg, lattice=15), P
+    return W.workload(name)
+
+
+@pytest.mark.parametrize("name,steps", [("c1", 300), ("c2_small", 200), ("c3_small", 60), ("c4_small", 60),
+                                        ("c3_small_q15", 60)])
 def test_workloads_f64(gpu, oracle_mod, name, steps):
-    cfg, P = W.workload(name)
+    cfg, P = workload_case(name)
     sim, ref = run_pair(gpu, oracle_mod, cfg, P, steps, "f64")
     e = field_errors(sim.fields(), ref.fields())
     assert max(e.values()) < 1e-9, e
@@ -137,10 +148,11 @@ def test_workloads_f64(gpu, oracle_mod, name, steps):
     assert np.allclose(q[:, 14], rq[:, 14], rtol=1e-10, atol=1e-12)
 
 
-@pytest.mark.parametrize("name,steps", [("c1", 1000), ("c2_small", 1000), ("c3_small", 1000), ("c4_small", 1000)])
+@pytest.mark.parametrize("name,steps", [("c1", 1000), ("c2_small", 1000), ("c3_small", 1000), ("c4_small", 1000),
+                                        ("c4_small_q15", 1000)])
 def test_workloads_f32_1000_steps(gpu, oracle_mod, name, steps):
     """The stated FP32 bar: fields <= 1e-5 relative, positions <= 1e-4 lu."""
-    cfg, P = W.workload(name)
+    cfg, P = workload_case(name)
     sim, ref = run_pair(gpu, oracle_mod, cfg, P, steps, "f32")
     e = field_errors(sim.fields(), ref.fields())
     print(name, "f32 field errors", e)
