@@ -219,7 +219,7 @@ def main() -> int:
     ap.add_argument("--variants", default="f16,bf16,q15,mlp",
                     help="extra storage formats timed beside the main one, 'q15' for the D3Q15 flow lattice "
                          "(FP32, 3D workloads) and 'mlp' for the learned part")
-    ap.add_argument("--cpu-steps", type=int, default=2)
+    ap.add_argument("--cpu-steps", type=int, default=4)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--empty", action="store_true", help="analysis: the same lattice without particles")
     ap.add_argument("--no-copy-probe", action="store_true")
