@@ -285,7 +285,10 @@ int make_plan(const pibm_params *p, const pibm_particle *pt, int np, Plan &P)
     const long long npa = std::max(np, 1);
     size_t sz[R_COUNT];
     const size_t fbytes = (size_t)P.Q * P.Ns * P.ssize, gbytes = (size_t)P.QG * P.Ns * P.ssize;
-    sz[R_FA] = fbytes; sz[R_GA] = gbytes; sz[R_FB] = fbytes; sz[R_GB] = gbytes;
+    // an f copy also holds pibm_fields' output (rho, u, T: five compute-type
+    // arrays) while it is idle, which is larger for 16-bit 2D storage
+    const size_t fcopy = std::max<size_t>(fbytes, (size_t)5 * (size_t)P.Ns * P.tsize);
+    sz[R_FA] = fcopy; sz[R_GA] = gbytes; sz[R_FB] = fcopy; sz[R_GB] = gbytes;
     sz[R_PART0] = sz[R_PART1] = npa * sizeof(DevParticle);
     sz[R_REACT] = npa * sizeof(DevReact);
     sz[R_TMPL] = std::max(P.ntmpl_mk, 1LL) * sizeof(double4);
