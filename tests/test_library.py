@@ -49,6 +49,27 @@ def test_workspace_bytes_and_validation(L):
     assert L.pibm_workspace_bytes(ctypes.byref(bad), parts, len(P)) == 0
 
 
+def test_lattice_and_interpolation_options_validated(L):
+    """D3Q15 is accepted in 3D with FP32/FP64 storage and sized for 15 + 7
+    populations; D3Q15 in 2D or with 16-bit storage, and interpolation orders
+    other than 2 and 4, are refused (the sizing call returns 0)."""
+    cfg, P = W.workload("c3_small")
+    parts = pibm.make_particles(P)
+    size = lambda c, st="f32": L.pibm_workspace_bytes(ctypes.byref(pibm.make_params(c, st)), parts, len(P))
+    n19, n15 = size(cfg), size(dict(cfg, lattice=15))
+    N = cfg["nx"] * cfg["ny"] * cfg["nz"]
+    assert n15 > 0 and n19 - n15 >= 2 * 4 * N * 4          # four fewer flow populations, two copies
+    assert size(dict(cfg, lattice=15), "f64") > 0
+    assert size(dict(cfg, lattice=15), "f16") == 0
+    assert size(dict(cfg, lattice=15), "bf16") == 0
+    assert size(dict(cfg, lattice=17)) == 0
+    c2, P2 = W.workload("c1")
+    assert L.pibm_workspace_bytes(ctypes.byref(pibm.make_params(dict(c2, lattice=15))),
+                                  pibm.make_particles(P2), len(P2)) == 0
+    assert size(dict(cfg, interp_order=4)) > 0
+    assert size(dict(cfg, interp_order=3)) == 0
+
+
 def test_full_size_workspace_fits_hbm(L):
     """Every workload fits one MI355X (288 GB) with room to spare."""
     for name in ("c2", "c3", "c4"):
