@@ -38,7 +38,7 @@ class OrcParams(ctypes.Structure):
         ("n_sub", ctypes.c_int),
         ("beta_p", ctypes.c_double), ("c_r", ctypes.c_double),
         ("marker_mode", ctypes.c_int), ("marker_spacing", ctypes.c_double),
-        ("interp_order", ctypes.c_int), ("lattice", ctypes.c_int),
+        ("interp_order", ctypes.c_int), ("lattice", ctypes.c_int), ("thermal_model", ctypes.c_int),
     ]
 
 
@@ -97,7 +97,7 @@ def lib():
 def derive(cfg: dict) -> dict:
     """Relaxation times and g*beta from the configuration (see module doc)."""
     dim = cfg["dim"]
-    csg2 = 1.0 / 3.0 if dim == 2 else 0.25
+    csg2 = 1.0 / 3.0 if dim == 2 or int(cfg.get("thermal_model", 0)) == 1 else 0.25
     if cfg.get("Ra", 0.0) > 0:
         Ra, Pr, Lc, uc = cfg["Ra"], cfg["Pr"], cfg["Lc"], cfg["uc"]
         nu = math.sqrt(Pr) * Lc * uc / math.sqrt(Ra)
@@ -145,6 +145,7 @@ def make_params(cfg: dict) -> OrcParams:
     p.marker_mode = int(cfg.get("marker_mode", 0))
     p.interp_order = int(cfg.get("interp_order", 2))
     p.lattice = int(cfg.get("lattice", 19))
+    p.thermal_model = int(cfg.get("thermal_model", 0))
     p.marker_spacing = cfg.get("marker_spacing", 1.0)
     return p
 
@@ -169,7 +170,7 @@ class Oracle:
         self.shape = (self.params.nz, self.params.ny, self.params.nx)
         self.N = int(L.orc_num_nodes(self._h))
         self.Q = 9 if self.dim == 2 else (15 if int(cfg.get("lattice", 19)) == 15 else 19)
-        self.Qg = 5 if self.dim == 2 else 7
+        self.Qg = self.Q if int(cfg.get("thermal_model", 0)) == 1 else (5 if self.dim == 2 else 7)
 
     def __del__(self):
         h = getattr(self, "_h", None)

@@ -63,6 +63,7 @@ typedef struct {
     double marker_spacing;
     int interp_order;        /* Lagrange nodes per axis in Eq. (lbm6): 2 (0 means 2) or 4 */
     int lattice;             /* 3D flow velocity set: 19 (0 means 19) or 15 (Sec. 2.1's D3Q15) */
+    int thermal_model;       /* 0: D2Q5 / D3Q7, linear g^eq; 1: the flow lattice, quadratic g^eq */
 } orc_params;
 
 enum { ORC_FIXED = 1, ORC_THERMO = 2 };
@@ -89,9 +90,9 @@ typedef struct {
 typedef struct {
     orc_params p;
     int Q, Qg;
-    int e[19][3], eg[7][3];
-    double w[19], wg[7], csg2;
-    int opp[19], oppg[7];
+    int e[19][3], eg[19][3];
+    double w[19], wg[19], csg2;
+    int opp[19], oppg[19];
     long N;
     double *f, *g;           /* post-collision populations, [node][q] */
     double *fs, *gs;         /* scratch: post-stream populations */
@@ -156,6 +157,16 @@ static void set_lattice(orc_state *s)
             s->wg[a] = a == 0 ? 1.0/4.0 : 1.0/8.0;
         }
         s->csg2 = 1.0/4.0;
+    }
+    if (s->p.thermal_model == 1) {
+        /* Sec. 2.1 as printed: temperature on the flow lattice with the same
+         * weights and c_s^2 = 1/3 (its equilibrium is quadratic, see geq) */
+        s->Qg = s->Q;
+        for (int a = 0; a < s->Q; a++) {
+            for (int d = 0; d < 3; d++) s->eg[a][d] = s->e[a][d];
+            s->wg[a] = s->w[a];
+        }
+        s->csg2 = 1.0/3.0;
     }
     for (int a = 0; a < s->Q; a++)
         for (int b = 0; b < s->Q; b++)
@@ -258,6 +269,11 @@ static double feq(const orc_state *s, int a, double rho, const double u[3])
 static double geq(const orc_state *s, int a, double T, const double u[3])
 {
     double eu = s->eg[a][0]*u[0] + s->eg[a][1]*u[1] + s->eg[a][2]*u[2];
+    if (s->p.thermal_model == 1) {
+        /* the flow's equilibrium form with T in place of rho (Sec. 2.1) */
+        double uu = u[0]*u[0] + u[1]*u[1] + u[2]*u[2];
+        return s->wg[a] * T * (1.0 + 3.0*eu + 4.5*eu*eu - 1.5*uu);
+    }
     return s->wg[a] * T * (1.0 + eu / s->csg2);
 }
 

@@ -211,14 +211,16 @@ def test_poiseuille_second_order_off_magic(oracle_mod):
     assert errs[1] < errs[0] / 3.0
 
 
+@pytest.mark.parametrize("thermal_model", [0, 1])
 @pytest.mark.parametrize("dim", [2, 3])
-def test_conduction_between_dirichlet_walls(oracle_mod, dim):
+def test_conduction_between_dirichlet_walls(oracle_mod, dim, thermal_model):
     """P6: pure conduction between anti-bounce-back walls at T = 1 and 0:
-    the steady profile is linear with the wall values at the halfway planes."""
+    the steady profile is linear with the wall values at the halfway planes
+    (D2Q5 / D3Q7, and the flow lattice with the quadratic equilibrium)."""
     n = 10
     mk = base2d if dim == 2 else base3d
     cfg = mk(nx=n, ny=2, nz=2, periodic=[0, 1, 1], T_wall=[1.0, 0.0, 0, 0, 0, 0], T_init=0.5,
-             T_ref=0.5, tau_g=1.1)
+             T_ref=0.5, tau_g=1.1, thermal_model=thermal_model)
     o = oracle_mod.Oracle(cfg)
     o.step(4000)
     rho, u, T = o.fields()
@@ -588,7 +590,48 @@ def _fd_laplace_nu(M, Ar):
     return 0.5 * (T[1, :].sum() + T[-2, :].sum() + T[:, 1].sum() + T[:, -2].sum())
 
 
-def test_conduction_annulus_nusselt_vs_laplace(oracle_mod):
+@pytest.mark.parametrize("thermal_model", [0, 1])
+@pytest.mark.parametrize("tau_g", [0.8, 1.2])
+def test_thermal_advection_diffusion_closed_form(oracle_mod, thermal_model, tau_g):
+    """A temperature sine T = 1/2 + A sin(k x) in a uniform flow u0 along x
+    (periodic) is carried at u0 and decays at alpha_eff k^2.  On the flow
+    lattice with the quadratic equilibrium (Sec. 2.1 as printed) alpha_eff =
+    alpha = (tau_g - 1/2) / 3.  The linear D2Q5 equilibrium lacks the (e.u)^2
+    term and leaves the known error alpha_eff = alpha - u0^2 (tau_g - 1/2).
+    The two differ by 3% here, so a mix-up of the models fails."""
+    n, u0, A, steps = 64, 0.1, 0.1, 400
+    cfg = base2d(nx=n, ny=4, periodic=[1, 1, 0], tau_f=0.8, tau_g=tau_g, thermal_model=thermal_model)
+    o = oracle_mod.Oracle(cfg)
+    # standard D2Q9 and its first five directions (D2Q5), in the populations' order
+    e = np.array([[0, 0], [1, 0], [0, 1], [-1, 0], [0, -1], [1, 1], [-1, 1], [-1, -1], [1, -1]], dtype=float)
+    w9 = np.array([4 / 9] + [1 / 9] * 4 + [1 / 36] * 4)
+    x = np.indices(o.shape)[2].ravel().astype(float)
+    k = 2.0 * math.pi / n
+    T = 0.5 + A * np.sin(k * x)
+    eu = e[:, 0] * u0
+    feq = w9 * (1.0 + 3.0 * eu + 4.5 * eu ** 2 - 1.5 * u0 ** 2)
+    f = feq[:, None] * np.ones((1, o.N))
+    if thermal_model == 1:
+        g = feq[:, None] * T[None, :]
+    else:
+        w5 = np.array([1 / 3] + [1 / 6] * 4)
+        g = (w5 * (1.0 + 3.0 * eu[:5]))[:, None] * T[None, :]
+    o.set_populations(f, g)
+    o.step(steps)
+    prof = o.fields()[2][0].mean(0) - 0.5
+    xs = np.arange(n)
+    c = 2.0 / n * np.sum(prof * np.cos(k * xs))
+    s = 2.0 / n * np.sum(prof * np.sin(k * xs))
+    amp, shift = math.hypot(c, s), math.atan2(-c, s)     # prof = amp sin(k x - shift)
+    alpha = o.derived["alpha"]
+    expect = alpha if thermal_model == 1 else alpha - u0 ** 2 * (tau_g - 0.5)
+    assert abs(-math.log(amp / A) / steps / (expect * k * k) - 1.0) < 0.01
+    dphi = (shift - k * u0 * steps + math.pi) % (2.0 * math.pi) - math.pi
+    assert abs(dphi) < 1e-2
+
+
+@pytest.mark.parametrize("thermal_model", [0, 1])
+def test_conduction_annulus_nusselt_vs_laplace(oracle_mod, thermal_model):
     """P7: with buoyancy off, the cavity with the hot cylinder is pure
     conduction.  The PIBM heat exchange (kappa_T = 1) and the Nusselt number of
     Sec. 3.1 (Nu = sum (T_p - T_l) A_l / (k dT)) must agree with a brute-force
@@ -596,7 +639,7 @@ def test_conduction_annulus_nusselt_vs_laplace(oracle_mod):
     extrapolation) within 3% at 64^2; the textbook shape factor of a centred
     cylinder, pi / ln(1.08 Ar), is a second check of the reference value."""
     cfg, P = W.workload("c1")
-    cfg.update(gbeta=0.0, tau_g=1.5)
+    cfg.update(gbeta=0.0, tau_g=1.5, thermal_model=thermal_model)
     o = oracle_mod.Oracle(cfg, P)
     o.step(4000)
     nu_lbm = o.reactions()[0, 7] / o.derived["alpha"]
