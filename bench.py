@@ -216,9 +216,10 @@ def main() -> int:
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--workload", default="c3", choices=sorted(WORKLOAD_TEXT))
     ap.add_argument("--storage", default="f32", choices=sorted(STORAGE_BYTES))
-    ap.add_argument("--variants", default="f16,bf16,q15,mlp",
+    ap.add_argument("--variants", default="f16,bf16,q15,literal,mlp",
                     help="extra storage formats timed beside the main one, 'q15' for the D3Q15 flow lattice "
-                         "(FP32, 3D workloads) and 'mlp' for the learned part")
+                         "(FP32, 3D workloads), 'literal' for D3Q15 with temperature on the flow lattice "
+                         "(quadratic equilibrium, FP32) and 'mlp' for the learned part")
     ap.add_argument("--cpu-steps", type=int, default=4)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--empty", action="store_true", help="analysis: the same lattice without particles")
@@ -249,9 +250,14 @@ def main() -> int:
 
     variants = {}
     for st in [s for s in args.variants.split(",") if s and s != args.storage and s != "mlp"]:
-        if st == "q15" and cfg["dim"] != 3:
+        if st in ("q15", "literal") and cfg["dim"] != 3:
             continue
-        vcfg, vst = (W.with_overrides(cfg, lattice=15), "f32") if st == "q15" else (cfg, st)
+        if st == "q15":
+            vcfg, vst = W.with_overrides(cfg, lattice=15), "f32"
+        elif st == "literal":
+            vcfg, vst = W.with_overrides(cfg, lattice=15, thermal_model=1), "f32"
+        else:
+            vcfg, vst = cfg, st
         r = time_gpu(vcfg, P, vst, max(args.steps // 2, 10), args.warmup, profile=True)
         lms, ln = r["prof"]["lattice"]
         n_steps = max(args.steps // 2, 10)

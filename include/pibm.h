@@ -106,6 +106,10 @@ typedef struct pibm_params {
                                 storage only); populations are ordered rest, +-x, +-y, +-z, then
                                 the corners (+,+,+) (-,-,-) (+,+,-) (-,-,+) (+,-,+) (-,+,-)
                                 (-,+,+) (+,-,-) */
+    int thermal_model;       /* 0: D2Q5 / D3Q7 with the linear equilibrium (default); 1: temperature
+                                on the flow lattice with the flow's quadratic equilibrium form and
+                                c_sg^2 = 1/3 (Sec. 2.1 as printed; FP32 and FP64 storage only; the
+                                wall of the last blocked axis sets a diagonal's Dirichlet value) */
 } pibm_params;
 
 enum { PIBM_FIXED = 1, PIBM_THERMO = 2 };

@@ -61,7 +61,8 @@ struct Plan {
     size_t off[R_COUNT + 1];
 };
 
-double derive_csg2(int dim) { return dim == 2 ? 1.0 / 3.0 : 0.25; }
+// c_sg^2 of the thermal lattice: D2Q5 1/3, D3Q7 1/4, the flow lattice 1/3
+double derive_csg2(const pibm_params &p) { return p.dim == 2 || p.thermal_model == 1 ? 1.0 / 3.0 : 0.25; }
 
 struct Derived {
     double tau_f, tau_g, gbeta, nu, alpha;
@@ -81,9 +82,9 @@ Derived derive(const pibm_params &p)
         d.gbeta = p.Lc > 0 ? p.Gr * p.nu * p.nu / (p.Lc * p.Lc * p.Lc) : 0.0;
     }
     d.tau_f = 3.0 * d.nu + 0.5;
-    d.tau_g = d.alpha / derive_csg2(p.dim) + 0.5;
+    d.tau_g = d.alpha / derive_csg2(p) + 0.5;
     if (p.tau_f > 0) { d.tau_f = p.tau_f; d.nu = (p.tau_f - 0.5) / 3.0; }
-    if (p.tau_g > 0) { d.tau_g = p.tau_g; d.alpha = (p.tau_g - 0.5) * derive_csg2(p.dim); }
+    if (p.tau_g > 0) { d.tau_g = p.tau_g; d.alpha = (p.tau_g - 0.5) * derive_csg2(p); }
     if (p.gbeta_set) d.gbeta = p.gbeta;
     return d;
 }
@@ -170,6 +171,9 @@ int check_params(const pibm_params *p)
     // D3Q15 is a 3D flow lattice, built for the FP32 and FP64 storage
     if (p->lattice == 15 && (p->dim != 3 || (p->storage != PIBM_STORE_F32 && p->storage != PIBM_STORE_F64)))
         return PIBM_EINVAL;
+    // temperature on the flow lattice: FP32 and FP64 storage
+    if (p->thermal_model != 0 && p->thermal_model != 1) return PIBM_EINVAL;
+    if (p->thermal_model == 1 && p->storage != PIBM_STORE_F32 && p->storage != PIBM_STORE_F64) return PIBM_EINVAL;
     const Derived d = derive(*p);
     if (!(d.tau_f > 0.5) || !(d.tau_g > 0.5)) return PIBM_EINVAL;
     if (!std::isfinite(d.gbeta)) return PIBM_EINVAL;
@@ -183,7 +187,7 @@ int make_plan(const pibm_params *p, const pibm_particle *pt, int np, Plan &P)
     if (np < 0 || (np > 0 && !pt)) return PIBM_EINVAL;
     P.dim = p->dim;
     P.Q = p->dim == 2 ? 9 : (p->lattice == 15 ? 15 : 19);
-    P.QG = p->dim == 2 ? 5 : 7;
+    P.QG = p->thermal_model == 1 ? P.Q : (p->dim == 2 ? 5 : 7);
     P.N = (long long)p->nx * p->ny * p->nz;
     P.ssize = p->storage == PIBM_STORE_F64 ? 8 : (p->storage == PIBM_STORE_F32 ? 4 : 2);
     // Array stride: N rounded up to 256 bytes, plus 129 x 256 bytes.  A stride
@@ -710,17 +714,24 @@ int macro_impl(pibm_ctx *c)
     return launch_lbm<DIM, SF, true>(c);
 }
 
+// FP32 / FP64 instances: flow lattice (D2Q9, D3Q19 or D3Q15) x thermal model
+// (D2Q5 / D3Q7 linear, or the flow lattice with the quadratic equilibrium)
+template <template <int, class> class F, class SF, typename... A>
+int dispatch_lattices(pibm_ctx *c, A... args)
+{
+    const bool qt = c->p.thermal_model == 1;
+    if (c->p.dim == 2) return qt ? F<2, OnQuadT<SF>>::run(c, args...) : F<2, SF>::run(c, args...);
+    if (c->p.lattice == 15) return qt ? F<3, OnQuadT<OnQ15<SF>>>::run(c, args...) : F<3, OnQ15<SF>>::run(c, args...);
+    return qt ? F<3, OnQuadT<SF>>::run(c, args...) : F<3, SF>::run(c, args...);
+}
+
 template <template <int, class> class F, typename... A>
 int dispatch(pibm_ctx *c, A... args)
 {
     const bool d3 = c->p.dim == 3;
     switch (c->p.storage) {
-    case PIBM_STORE_F32:
-        if (d3 && c->p.lattice == 15) return F<3, OnQ15<StF32>>::run(c, args...);
-        return d3 ? F<3, StF32>::run(c, args...) : F<2, StF32>::run(c, args...);
-    case PIBM_STORE_F64:
-        if (d3 && c->p.lattice == 15) return F<3, OnQ15<StF64>>::run(c, args...);
-        return d3 ? F<3, StF64>::run(c, args...) : F<2, StF64>::run(c, args...);
+    case PIBM_STORE_F32: return dispatch_lattices<F, StF32>(c, args...);
+    case PIBM_STORE_F64: return dispatch_lattices<F, StF64>(c, args...);
     case PIBM_STORE_F16DEV: return d3 ? F<3, StF16>::run(c, args...) : F<2, StF16>::run(c, args...);
     default: return d3 ? F<3, StBF16>::run(c, args...) : F<2, StBF16>::run(c, args...);
     }
@@ -747,8 +758,8 @@ template <int DIM, class SF> struct InitOp {
     static int run(pibm_ctx *c) {
         using T = typename SF::T;
         const int g = (int)std::min<long long>(4096, (c->P.N + 255) / 256);
-        hipLaunchKernelGGL((k_init<SF, Lat<DIM>::QG>), dim3(g), dim3(256), 0, c->stream, c->r(R_FA), c->r(R_GA),
-                           Lat<DIM>::Q, c->P.N, c->P.Ns, (T)(c->p.T_init - c->p.T_ref), Lat<DIM>::wg(0), Lat<DIM>::wg(1));
+        hipLaunchKernelGGL((k_init<SF, LatOf<DIM, SF>>), dim3(g), dim3(256), 0, c->stream, c->r(R_FA), c->r(R_GA),
+                           c->P.N, c->P.Ns, (T)(c->p.T_init - c->p.T_ref));
         return hip_ok(c, hipGetLastError());
     }
 };
@@ -790,7 +801,10 @@ double wf(int dim, int lattice, int q)
 {
     return dim == 2 ? Lat<2>::w(q) : (lattice == 15 ? LatT<3, 15>::w(q) : Lat<3>::w(q));
 }
-double wgt(int dim, int q) { return dim == 2 ? Lat<2>::wg(q) : Lat<3>::wg(q); }
+double wgt(int dim, int lattice, int thermal_model, int q)
+{
+    return thermal_model == 1 ? wf(dim, lattice, q) : (dim == 2 ? Lat<2>::wg(q) : Lat<3>::wg(q));
+}
 
 DevParticle to_dev(const pibm_particle &q, int tmpl)
 {
@@ -1025,7 +1039,7 @@ int pibm_get_populations(pibm_ctx *c, double *f, double *g)
         for (size_t n = 0; n < N; ++n) f[q * N + n] = wf(dim, c->p.lattice, q) + stored_to_dev(c, hf.data(), q * Ns + n, wf(dim, c->p.lattice, q));
     for (int q = 0; q < QG; ++q)
         for (size_t n = 0; n < N; ++n)
-            g[q * N + n] = wgt(dim, q) * c->p.T_ref + stored_to_dev(c, hg.data(), q * Ns + n, wgt(dim, q));
+            g[q * N + n] = wgt(dim, c->p.lattice, c->p.thermal_model, q) * c->p.T_ref + stored_to_dev(c, hg.data(), q * Ns + n, wgt(dim, c->p.lattice, c->p.thermal_model, q));
     return st;
 }
 
@@ -1040,7 +1054,7 @@ int pibm_set_populations(pibm_ctx *c, const double *f, const double *g)
         for (size_t n = 0; n < N; ++n) dev_to_stored(c, hf.data(), q * Ns + n, f[q * N + n] - wf(dim, c->p.lattice, q), wf(dim, c->p.lattice, q));
     for (int q = 0; q < QG; ++q)
         for (size_t n = 0; n < N; ++n)
-            dev_to_stored(c, hg.data(), q * Ns + n, g[q * N + n] - wgt(dim, q) * c->p.T_ref, wgt(dim, q));
+            dev_to_stored(c, hg.data(), q * Ns + n, g[q * N + n] - wgt(dim, c->p.lattice, c->p.thermal_model, q) * c->p.T_ref, wgt(dim, c->p.lattice, c->p.thermal_model, q));
     hipError_t e = hipMemcpyAsync(c->r(c->cur ? R_FB : R_FA), hf.data(), hf.size(), hipMemcpyHostToDevice, c->stream);
     if (e == hipSuccess) e = hipMemcpyAsync(c->r(c->cur ? R_GB : R_GA), hg.data(), hg.size(), hipMemcpyHostToDevice, c->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(c->stream);

@@ -20,6 +20,7 @@
 #include <hip/hip_runtime.h>
 #include <hip/hip_fp16.h>
 #include <stdint.h>
+#include <type_traits>
 
 namespace pibm {
 
@@ -43,6 +44,7 @@ template <> struct LatT<2, 9> {
     __host__ __device__ static constexpr double w(int q) { return q == 0 ? 4.0 / 9.0 : (q < 5 ? 1.0 / 9.0 : 1.0 / 36.0); }
     __host__ __device__ static constexpr double wg(int q) { return q == 0 ? 1.0 / 3.0 : 1.0 / 6.0; }
     static constexpr double csg2_inv = 3.0;
+    static constexpr bool QT = false;      // thermal equilibrium linear in u
 };
 
 template <> struct LatT<3, 19> {
@@ -60,6 +62,7 @@ template <> struct LatT<3, 19> {
     __host__ __device__ static constexpr double w(int q) { return q == 0 ? 1.0 / 3.0 : (q < 7 ? 1.0 / 18.0 : 1.0 / 36.0); }
     __host__ __device__ static constexpr double wg(int q) { return q == 0 ? 0.25 : 0.125; }
     static constexpr double csg2_inv = 4.0;
+    static constexpr bool QT = false;
 };
 
 // D3Q15 (Sec. 2.1): rest; +-x, +-y, +-z; then the 8 corners in opposite pairs
@@ -78,6 +81,7 @@ template <> struct LatT<3, 15> {
     __host__ __device__ static constexpr double w(int q) { return q == 0 ? 2.0 / 9.0 : (q < 7 ? 1.0 / 9.0 : 1.0 / 72.0); }
     __host__ __device__ static constexpr double wg(int q) { return q == 0 ? 0.25 : 0.125; }
     static constexpr double csg2_inv = 4.0;
+    static constexpr bool QT = false;
 };
 
 template <int DIM> using Lat = LatT<DIM, DIM == 2 ? 9 : 19>;
@@ -102,13 +106,29 @@ static_assert(lattice_ok<LatT<2, 9>>(), "D2Q9 table");
 static_assert(lattice_ok<LatT<3, 19>>(), "D3Q19 table");
 static_assert(lattice_ok<LatT<3, 15>>(), "D3Q15 table");
 
-// The flow lattice of a kernel instance travels with its storage traits: a
-// traits class with QF = 15 selects D3Q15, any other the default lattice.
+// Temperature on the flow lattice itself, with the flow's quadratic
+// equilibrium form (Sec. 2.1 as printed): every flow direction, the flow
+// weights, c_sg^2 = 1/3.
+template <class L> struct SameThermal : L {
+    static constexpr int QG = L::Q;
+    __host__ __device__ static constexpr double wg(int q) { return L::w(q); }
+    static constexpr double csg2_inv = 3.0;
+    static constexpr bool QT = true;
+};
+
+// The lattices of a kernel instance travel with its storage traits: a traits
+// class with QF = 15 selects D3Q15 for the flow, one with QTH = 1 the
+// temperature on the flow lattice; otherwise the defaults.
 template <class Base> struct OnQ15 : Base { static constexpr int QF = 15; };
+template <class Base> struct OnQuadT : Base { static constexpr int QTH = 1; };
 template <class SF, class = void> struct FlowQ { static constexpr int value = 0; };
 template <class SF> struct FlowQ<SF, decltype((void)SF::QF)> { static constexpr int value = SF::QF; };
+template <class SF, class = void> struct ThermQ { static constexpr int value = 0; };
+template <class SF> struct ThermQ<SF, decltype((void)SF::QTH)> { static constexpr int value = SF::QTH; };
 template <int DIM, class SF>
-using LatOf = LatT<DIM, DIM == 3 && FlowQ<SF>::value == 15 ? 15 : (DIM == 2 ? 9 : 19)>;
+using FlowLatOf = LatT<DIM, DIM == 3 && FlowQ<SF>::value == 15 ? 15 : (DIM == 2 ? 9 : 19)>;
+template <int DIM, class SF>
+using LatOf = typename std::conditional<ThermQ<SF>::value == 1, SameThermal<FlowLatOf<DIM, SF>>, FlowLatOf<DIM, SF>>::type;
 
 // --------------------------------------------------------------------------
 // Counter-based uniform numbers for stochastic rounding: a 32-bit integer
@@ -336,6 +356,7 @@ __device__ __forceinline__ void pull(const LbmArgs<T> &a, int x, int y, int z, T
     const uint32_t self = oz[1] + oy[1] + ox[1];
     S fr[L::Q], gr[L::QG];
     bool gv[L::QG];
+    int gface[L::QG];
 #pragma unroll
     for (int q = 0; q < L::Q; ++q) {
         const int ex = L::e(q, 0) + 1, ey = L::e(q, 1) + 1, ez = L::e(q, 2) + 1;
@@ -349,6 +370,9 @@ __device__ __forceinline__ void pull(const LbmArgs<T> &a, int x, int y, int z, T
         const int ex = L::e(q, 0) + 1, ey = L::e(q, 1) + 1, ez = L::e(q, 2) + 1;
         const int o = L::opp(q), lo = q < o ? q : o;
         gv[q] = vx[ex] && vy[ey] && vz[ez];
+        // the wall that blocks the direction (the last blocked axis when a
+        // diagonal meets an edge) sets the Dirichlet temperature
+        gface[q] = !vz[ez] ? 4 + (ez == 2 ? 0 : 1) : (!vy[ey] ? 2 + (ey == 2 ? 0 : 1) : (ex == 2 ? 0 : 1));
         const uint32_t off = gv[q] ? (uint32_t)(q - lo) * Ns + (oz[ez] + oy[ey] + ox[ex]) : (uint32_t)(o - lo) * Ns + self;
         gr[q] = load_at(ga + (size_t)lo * a.Ns, off);
     }
@@ -358,11 +382,8 @@ __device__ __forceinline__ void pull(const LbmArgs<T> &a, int x, int y, int z, T
     for (int q = 0; q < L::Q; ++q) f[q] = SF::cvt(fr[q], L::w(q));
 #pragma unroll
     for (int q = 0; q < L::QG; ++q) {
-        // the one axis of a D2Q5 / D3Q7 direction decides the wall face
-        const int d = L::e(q, 0) != 0 ? 0 : (L::e(q, 1) != 0 ? 1 : 2);
-        const int face = 2 * d + (L::e(q, d) > 0 ? 0 : 1);
         const TG val = (TG)SF::cvt(gr[q], L::wg(q));
-        g[q] = gv[q] ? val : -val + (TG)(2.0 * L::wg(q) * a.tw[q == 0 ? 0 : face]);
+        g[q] = gv[q] ? val : -val + (TG)(2.0 * L::wg(q) * a.tw[gface[q]]);
     }
 }
 
@@ -774,8 +795,10 @@ __global__ __launch_bounds__(LBM_THREADS) void k_lbm(LbmArgs<typename SF::T> a)
         }
         // Thermal BGK with the linear equilibrium and the heat source
         // (Eqs. lbm2.5, lbm12.5): inc = w (gg Q_B + omega_g dT) +- omega_g w T e.u / c_sg^2 - omega_g g.
+        // With temperature on the flow lattice the equilibrium is quadratic
+        // (Sec. 2.1): the symmetric part gains omega_g T (4.5 (e.u)^2 - 1.5 u.u).
         const C Tabs = (C)a.Tref + dT;
-        const C R = gg * QB + omg * dT;
+        const C R = gg * QB + omg * dT + (L::QT ? -(C)1.5 * omg * Tabs * uu : (C)0);
         const C Z = omg * Tabs * (C)L::csg2_inv;
         SF::st_sum(addr_at(gb, n), (T)g[0], (C)L::wg(0) * R - omg * g[0], L::wg(0), SR ? sr_bits(seed, L::Q) : 0u);
 #pragma unroll
@@ -789,7 +812,7 @@ __global__ __launch_bounds__(LBM_THREADS) void k_lbm(LbmArgs<typename SF::T> a)
                 else if (L::e(q, d) < 0) eu -= u[d];
             }
             const C wq = (C)L::wg(q);
-            const C P = wq * R, M = wq * Z * eu;
+            const C P = wq * (L::QT ? R + (C)4.5 * omg * Tabs * eu * eu : R), M = wq * Z * eu;
             S *pb = gb + (size_t)q * a.Ns;
             SF::st_sum(addr_at(pb, n), (T)g[q], (P + M) - omg * g[q], L::wg(q), SR ? sr_bits(seed, L::Q + q) : 0u);
             SF::st_sum(addr_at(pb, (uint32_t)(o - q) * (uint32_t)a.Ns + n), (T)g[o], (P - M) - omg * g[o], L::wg(o),
@@ -1919,16 +1942,14 @@ __global__ void k_dem(DemArgs a)
 
 // Initial state: f = w rho0 and g = w T_init, i.e. deviations 0 and
 // w (T_init - T_ref).
-template <class SF, int QG>
-__global__ void k_init(void *f, void *g, int Q, long long N, long long Ns, typename SF::T dTinit, double wg0, double wg1)
+template <class SF, class L>
+__global__ void k_init(void *f, void *g, long long N, long long Ns, typename SF::T dTinit)
 {
     using S = typename SF::S;
     for (long long n = blockIdx.x * (long long)blockDim.x + threadIdx.x; n < N; n += (long long)gridDim.x * blockDim.x) {
-        for (int q = 0; q < Q; ++q) SF::st((S *)f + (size_t)q * Ns + n, (typename SF::T)0, 1.0);
-        for (int q = 0; q < QG; ++q) {
-            const double w = q == 0 ? wg0 : wg1;
-            SF::st((S *)g + (size_t)q * Ns + n, (typename SF::T)(w * (double)dTinit), w);
-        }
+        for (int q = 0; q < L::Q; ++q) SF::st((S *)f + (size_t)q * Ns + n, (typename SF::T)0, 1.0);
+        for (int q = 0; q < L::QG; ++q)
+            SF::st((S *)g + (size_t)q * Ns + n, (typename SF::T)(L::wg(q) * (double)dTinit), L::wg(q));
     }
 }
 

@@ -45,7 +45,7 @@ class Params(ctypes.Structure):
         ("gravity", ctypes.c_double), ("kappa_T", ctypes.c_double), ("E_star", ctypes.c_double),
         ("poisson", ctypes.c_double), ("mu_fric", ctypes.c_double), ("n_sub", ctypes.c_int),
         ("beta_p", ctypes.c_double), ("c_r", ctypes.c_double), ("skin", ctypes.c_double),
-        ("interp_order", ctypes.c_int), ("lattice", ctypes.c_int),
+        ("interp_order", ctypes.c_int), ("lattice", ctypes.c_int), ("thermal_model", ctypes.c_int),
     ]
 
 
@@ -153,6 +153,7 @@ def make_params(cfg: dict, storage: str = "f32") -> Params:
     p.skin = float(cfg.get("skin", 1.0))
     p.interp_order = int(cfg.get("interp_order", 2))
     p.lattice = int(cfg.get("lattice", 19))
+    p.thermal_model = int(cfg.get("thermal_model", 0))
     return p
 
 
@@ -208,7 +209,7 @@ class Simulation:
         self.shape = (self.params.nz, self.params.ny, self.params.nx)
         self.N = int(L.pibm_num_nodes(self._h))
         self.Q = 9 if self.dim == 2 else (15 if int(cfg.get("lattice", 19)) == 15 else 19)
-        self.Qg = 5 if self.dim == 2 else 7
+        self.Qg = self.Q if int(cfg.get("thermal_model", 0)) == 1 else (5 if self.dim == 2 else 7)
         d = np.empty(5)
         L.pibm_derived(self._h, _dp(d))
         self.derived = dict(tau_f=d[0], tau_g=d[1], gbeta=d[2], nu=d[3], alpha=d[4])

@@ -71,6 +71,8 @@ def main(argv=None) -> int:
     ap.add_argument("--max-steps", type=int, default=600000)
     ap.add_argument("--interp-order", type=int, default=2, help="Lagrange nodes per axis, Eq. (lbm6): 2 or 4")
     ap.add_argument("--marker-mode", type=int, default=1, help="0 surface elements, 1 the paper's pi s^2 / 4")
+    ap.add_argument("--thermal-model", type=int, default=0,
+                    help="0 D2Q5 linear equilibrium, 1 the flow lattice with the quadratic equilibrium (Sec. 2.1)")
     args = ap.parse_args(argv)
     from . import pibm
 
@@ -80,9 +82,11 @@ def main(argv=None) -> int:
     rows = []
     for Ra, Ar in cases:
         nu, steps, ok, sec = run_case(pibm, args.n, Ra, Ar, args.storage, args.chunk, args.tol, args.max_steps, log,
-                                      interp_order=args.interp_order, marker_mode=args.marker_mode)
+                                      interp_order=args.interp_order, marker_mode=args.marker_mode,
+                                      thermal_model=args.thermal_model)
         ref = PRINTED.get((Ra, Ar))
         row = dict(Ra=Ra, Ar=Ar, n=args.n, interp_order=args.interp_order, marker_mode=args.marker_mode,
+                   thermal_model=args.thermal_model,
                    Nu=round(nu, 4), printed=ref,
                    rel_err=None if ref is None else round(nu / ref - 1.0, 4), steps=steps, converged=ok,
                    seconds=round(sec, 1))

@@ -82,13 +82,16 @@ def _box_particles(dim, n, seed):
     return np.array(rows)
 
 
-@pytest.mark.parametrize("dim,order,lattice", [(2, 2, 19), (3, 2, 19), (2, 4, 19), (3, 4, 19), (3, 2, 15)])
-def test_single_step_random_state_f64(gpu, oracle_mod, dim, order, lattice):
+@pytest.mark.parametrize("dim,order,lattice,tm", [(2, 2, 19, 0), (3, 2, 19, 0), (2, 4, 19, 0), (3, 4, 19, 0),
+                                                  (3, 2, 15, 0), (2, 2, 19, 1), (3, 2, 19, 1), (3, 2, 15, 1)])
+def test_single_step_random_state_f64(gpu, oracle_mod, dim, order, lattice, tm):
     """One step from a random non-equilibrium state on a ragged multi-tile
     box (x periodic, y and z walls): every population, and every particle's
     reactions and new state, agree with the oracle; with the multilinear
-    (i_max = 2) and the cubic (i_max = 4) interpolation of Eq. (lbm6), and on
-    the D3Q15 flow lattice of Sec. 2.1."""
+    (i_max = 2) and the cubic (i_max = 4) interpolation of Eq. (lbm6), on the
+    D3Q15 flow lattice of Sec. 2.1, and with temperature on the flow lattice
+    (quadratic equilibrium; tm = 1), walls at different temperatures meeting
+    at edges."""
     if dim == 2:
         cfg = dict(dim=2, nx=150, ny=37, nz=1, periodic=[1, 0, 0])
     else:
@@ -96,7 +99,7 @@ def test_single_step_random_state_f64(gpu, oracle_mod, dim, order, lattice):
     cfg.update(T_wall=[0.2, 0.7, 0.0, 1.0, 0.3, 0.6], T_init=0.4, T_ref=0.35, Ra=0.0, nu=0.05, Pr=0.7,
                Gr=300.0, Lc=8.0, gravity=2e-3, kappa_T=1.0, marker_mode=1, marker_spacing=1.0,
                E_star=50.0, poisson=0.33, mu_fric=0.3, n_sub=3, beta_p=0.05, c_r=1.0, interp_order=order,
-               lattice=lattice)
+               lattice=lattice, thermal_model=tm)
     P = _box_particles(dim, cfg["nx"], 7)
     P[0, 12] = W.THERMO
     sim = gpu.Simulation(cfg, P, storage="f64")
@@ -105,7 +108,7 @@ def test_single_step_random_state_f64(gpu, oracle_mod, dim, order, lattice):
     w = np.array([4 / 9] + [1 / 9] * 4 + [1 / 36] * 4) if dim == 2 else \
         (np.array([2 / 9] + [1 / 9] * 6 + [1 / 72] * 8) if lattice == 15 else
          np.array([1 / 3] + [1 / 18] * 6 + [1 / 36] * 12))
-    wg = np.array([1 / 3] + [1 / 6] * 4) if dim == 2 else np.array([1 / 4] + [1 / 8] * 6)
+    wg = w if tm == 1 else (np.array([1 / 3] + [1 / 6] * 4) if dim == 2 else np.array([1 / 4] + [1 / 8] * 6))
     f0 = W.perturbed_populations(11, Q, sim.N, w, 1.0, 0.05)
     g0 = W.perturbed_populations(12, Qg, sim.N, wg, 0.5, 0.2)
     sim.set_populations(f0, g0)
@@ -127,15 +130,19 @@ def test_single_step_random_state_f64(gpu, oracle_mod, dim, order, lattice):
 
 
 def workload_case(name):
-    """A named workload; the suffix _q15 puts it on the D3Q15 flow lattice."""
+    """A named workload; the suffix _q15 puts it on the D3Q15 flow lattice,
+    _tm1 puts the temperature on the flow lattice (quadratic equilibrium)."""
+    over = {}
+    if name.endswith("_tm1"):
+        name, over["thermal_model"] = name[:-4], 1
     if name.endswith("_q15"):
-        cfg, P = W.workload(name[:-4])
-        return W.with_overrides(cfg, lattice=15), P
-    return W.workload(name)
+        name, over["lattice"] = name[:-4], 15
+    cfg, P = W.workload(name)
+    return W.with_overrides(cfg, **over), P
 
 
 @pytest.mark.parametrize("name,steps", [("c1", 300), ("c2_small", 200), ("c3_small", 60), ("c4_small", 60),
-                                        ("c3_small_q15", 60)])
+                                        ("c3_small_q15", 60), ("c1_tm1", 300), ("c3_small_q15_tm1", 60)])
 def test_workloads_f64(gpu, oracle_mod, name, steps):
     cfg, P = workload_case(name)
     sim, ref = run_pair(gpu, oracle_mod, cfg, P, steps, "f64")

@@ -68,6 +68,12 @@ def test_lattice_and_interpolation_options_validated(L):
                                   pibm.make_particles(P2), len(P2)) == 0
     assert size(dict(cfg, interp_order=4)) > 0
     assert size(dict(cfg, interp_order=3)) == 0
+    # temperature on the flow lattice: 19 + 19 populations, FP32 / FP64 only
+    n_tm = size(dict(cfg, thermal_model=1))
+    assert n_tm - n19 >= 2 * 12 * N * 4
+    assert size(dict(cfg, thermal_model=1), "f64") > 0
+    assert size(dict(cfg, thermal_model=1), "f16") == 0
+    assert size(dict(cfg, thermal_model=2)) == 0
 
 
 def test_full_size_workspace_fits_hbm(L):
