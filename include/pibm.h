@@ -110,6 +110,11 @@ typedef struct pibm_params {
                                 on the flow lattice with the flow's quadratic equilibrium form and
                                 c_sg^2 = 1/3 (Sec. 2.1 as printed; FP32 and FP64 storage only; the
                                 wall of the last blocked axis sets a diagonal's Dirichlet value) */
+    int streams;             /* 0: automatic (two streams on lattices of at least 2^22 nodes, one
+                                below, where the cross-stream waits cost more than they hide);
+                                1: every launch on the caller's stream; 2: binning beside the
+                                exchange and the DEM beside the lattice kernel on a second stream.
+                                Results are identical for every choice. */
 } pibm_params;
 
 enum { PIBM_FIXED = 1, PIBM_THERMO = 2 };
@@ -132,9 +137,13 @@ size_t pibm_workspace_bytes(const pibm_params *p, const pibm_particle *particles
 /* Create a context.  dev_workspace: device pointer (>= pibm_workspace_bytes,
  * 256-byte aligned) owned by the caller and borrowed until pibm_destroy;
  * hip_stream: the caller's hipStream_t (NULL = default stream) on which all
- * work is queued.  Validates tau > 1/2, sizes, particle overlap and
- * containment; fills f = w rho0, g = w T_init; uploads particles.  Returns
- * after the uploads completed. */
+ * work is queued.  With two streams (pibm_params.streams) the context also
+ * owns one non-blocking stream on that stream's device: within a step,
+ * binning runs there beside the exchange and the DEM sub-steps beside the
+ * lattice kernel, forked from and joined back into hip_stream by events, so
+ * every call's work is complete once hip_stream is.  Validates tau > 1/2, sizes, particle overlap and containment; fills
+ * f = w rho0, g = w T_init; uploads particles.  Returns after the uploads
+ * completed; PIBM_EDEVICE if the stream or events cannot be created. */
 int pibm_init(pibm_ctx **out, const pibm_params *p, const pibm_particle *particles, int n_particles,
               void *dev_workspace, size_t workspace_bytes, void *hip_stream);
 

@@ -174,6 +174,7 @@ int check_params(const pibm_params *p)
     // temperature on the flow lattice: FP32 and FP64 storage
     if (p->thermal_model != 0 && p->thermal_model != 1) return PIBM_EINVAL;
     if (p->thermal_model == 1 && p->storage != PIBM_STORE_F32 && p->storage != PIBM_STORE_F64) return PIBM_EINVAL;
+    if (p->streams < 0 || p->streams > 2) return PIBM_EINVAL;
     const Derived d = derive(*p);
     if (!(d.tau_f > 0.5) || !(d.tau_g > 0.5)) return PIBM_EINVAL;
     if (!std::isfinite(d.gbeta)) return PIBM_EINVAL;
@@ -404,6 +405,13 @@ struct pibm_ctx {
     Plan P;
     Derived d;
     hipStream_t stream;
+    // Second stream on the same device: binning runs beside the marker
+    // kernel and the DEM sub-steps beside the lattice kernel.  Each step forks
+    // from `stream` and joins back into it, so all work stays ordered with
+    // respect to the caller's stream.
+    bool two = false;              // the step uses the second stream
+    hipStream_t side = nullptr;
+    hipEvent_t ev_start = nullptr, ev_bin = nullptr, ev_mk = nullptr, ev_join = nullptr;
     char *ws;
     size_t ws_bytes;
     int cur;        // lattice copy holding the current state (0 = A, 1 = B)
@@ -419,6 +427,12 @@ struct pibm_ctx {
     std::vector<hipEvent_t> ev_free;
     std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_rec[PIBM_NPHASE];
     void *r(int reg) const { return ws + P.off[reg]; }
+    ~pibm_ctx() {
+        if (side) (void)hipStreamSynchronize(side);
+        for (hipEvent_t e : {ev_start, ev_bin, ev_mk, ev_join})
+            if (e) (void)hipEventDestroy(e);
+        if (side) (void)hipStreamDestroy(side);
+    }
 };
 
 namespace {
@@ -461,7 +475,7 @@ int hip_ok(pibm_ctx *c, hipError_t e)
     return PIBM_EDEVICE;
 }
 
-int build_cells(pibm_ctx *c);
+int build_cells(pibm_ctx *c, hipStream_t s);
 
 template <int DIM, class SF>
 int launch_markers(pibm_ctx *c, bool reactions)
@@ -469,7 +483,7 @@ int launch_markers(pibm_ctx *c, bool reactions)
     using T = typename SF::T;
     if (c->P.np == 0) return PIBM_OK;
     int st;
-    if ((st = build_cells(c))) return st;          // the order of the workgroups (the DEM reuses the list)
+    if ((st = build_cells(c, c->stream))) return st;   // the order of the workgroups (the DEM reuses the list)
     MkArgs<T> m{};
     m.lb = lbm_args<T>(c);
     m.part = (const DevParticle *)c->r(c->pcur ? R_PART1 : R_PART0);
@@ -495,7 +509,7 @@ int launch_features(pibm_ctx *c, bool raw, bool for_network)
     using T = typename SF::T;
     if (c->P.np == 0) return PIBM_OK;
     int st;
-    if ((st = build_cells(c))) return st;
+    if ((st = build_cells(c, c->stream))) return st;
     FeatArgs<T> f{};
     f.lb = lbm_args<T>(c);
     f.ncx = c->P.ncx; f.ncy = c->P.ncy; f.ncz = c->P.ncz;
@@ -554,19 +568,19 @@ BinArgs bin_args(pibm_ctx *c)
     return b;
 }
 
-int launch_bin(pibm_ctx *c)
+int launch_bin(pibm_ctx *c, hipStream_t s)
 {
     if (c->P.np == 0) return PIBM_OK;
     BinArgs b = bin_args(c);
     const int nt = c->P.ntiles;
     int *cntr = (int *)c->r(R_CNTR);
-    hipLaunchKernelGGL(k_zero2, dim3(std::min(1024, (nt + 256) / 256)), dim3(256), 0, c->stream, b.tile_count, (long long)nt,
+    hipLaunchKernelGGL(k_zero2, dim3(std::min(1024, (nt + 256) / 256)), dim3(256), 0, s, b.tile_count, (long long)nt,
                        cntr, 1LL);
     const int gb = (c->P.np + BIN_THREADS / 64 - 1) / (BIN_THREADS / 64);
-    hipLaunchKernelGGL((k_bin<false>), dim3(gb), dim3(BIN_THREADS), 0, c->stream, b);
-    hipLaunchKernelGGL(k_alloc, dim3((nt + 255) / 256), dim3(256), 0, c->stream, (const int *)b.tile_count, b.tile_start,
+    hipLaunchKernelGGL((k_bin<false>), dim3(gb), dim3(BIN_THREADS), 0, s, b);
+    hipLaunchKernelGGL(k_alloc, dim3((nt + 255) / 256), dim3(256), 0, s, (const int *)b.tile_count, b.tile_start,
                        b.tile_fill, nt, cntr);
-    hipLaunchKernelGGL((k_bin<true>), dim3(gb), dim3(BIN_THREADS), 0, c->stream, b);
+    hipLaunchKernelGGL((k_bin<true>), dim3(gb), dim3(BIN_THREADS), 0, s, b);
 
     return hip_ok(c, hipGetLastError());
 }
@@ -612,33 +626,33 @@ DemArgs dem_args(pibm_ctx *c)
 }
 
 // Cell list of the current particle state (kept until the state changes).
-int build_cells(pibm_ctx *c)
+int build_cells(pibm_ctx *c, hipStream_t s)
 {
     if (c->P.np == 0 || c->cells_ok) return PIBM_OK;
     DemArgs a = dem_args(c);
     const int gb = (c->P.np + 127) / 128;
     a.cur = (const DevParticle *)c->r(c->pcur ? R_PART1 : R_PART0);
     int *cntr = (int *)c->r(R_CNTR) + 1;
-    hipLaunchKernelGGL(k_zero2, dim3(std::min(1024, (c->P.ncells + 256) / 256)), dim3(256), 0, c->stream,
+    hipLaunchKernelGGL(k_zero2, dim3(std::min(1024, (c->P.ncells + 256) / 256)), dim3(256), 0, s,
                        a.cell_count, (long long)c->P.ncells, cntr, 1LL);
-    hipLaunchKernelGGL((k_cells<false>), dim3(gb), dim3(128), 0, c->stream, a);
-    hipLaunchKernelGGL(k_alloc, dim3((c->P.ncells + 255) / 256), dim3(256), 0, c->stream, (const int *)a.cell_count,
+    hipLaunchKernelGGL((k_cells<false>), dim3(gb), dim3(128), 0, s, a);
+    hipLaunchKernelGGL(k_alloc, dim3((c->P.ncells + 255) / 256), dim3(256), 0, s, (const int *)a.cell_count,
                        a.cell_start, a.cell_fill, c->P.ncells, cntr);
-    hipLaunchKernelGGL((k_cells<true>), dim3(gb), dim3(128), 0, c->stream, a);
+    hipLaunchKernelGGL((k_cells<true>), dim3(gb), dim3(128), 0, s, a);
     c->cells_ok = 1;
     return hip_ok(c, hipGetLastError());
 }
 
-int launch_dem(pibm_ctx *c)
+int launch_dem(pibm_ctx *c, hipStream_t s)
 {
     if (c->P.np == 0) return PIBM_OK;
     int st;
-    if ((st = build_cells(c))) return st;
+    if ((st = build_cells(c, s))) return st;
     DemArgs a = dem_args(c);
     a.cur = (const DevParticle *)c->r(c->pcur ? R_PART1 : R_PART0);
     hipLaunchKernelGGL(k_neighbours, dim3((c->P.np + NBR_THREADS / 64 - 1) / (NBR_THREADS / 64)), dim3(NBR_THREADS), 0,
-                       c->stream, a);
-    for (int s = 0; s < c->p.n_sub; ++s) {
+                       s, a);
+    for (int k = 0; k < c->p.n_sub; ++k) {
         a.cur = (const DevParticle *)c->r(c->pcur ? R_PART1 : R_PART0);
         a.nxt = (DevParticle *)c->r(c->pcur ? R_PART0 : R_PART1);
         a.hid_in = (const int *)c->r(c->hcur ? R_HID1 : R_HID0);
@@ -647,8 +661,8 @@ int launch_dem(pibm_ctx *c)
         a.hid_out = (int *)c->r(c->hcur ? R_HID0 : R_HID1);
         a.hxi_out = (double *)c->r(c->hcur ? R_HXI0 : R_HXI1);
         a.hn_out = (int *)c->r(c->hcur ? R_HN0 : R_HN1);
-        a.last = s == c->p.n_sub - 1;
-        hipLaunchKernelGGL(k_dem, dim3((c->P.np + 127) / 128), dim3(128), 0, c->stream, a);
+        a.last = k == c->p.n_sub - 1;
+        hipLaunchKernelGGL(k_dem, dim3((c->P.np + 127) / 128), dim3(128), 0, s, a);
         c->pcur ^= 1;
         c->hcur ^= 1;
         c->cells_ok = 0;
@@ -672,13 +686,15 @@ hipEvent_t take_event(pibm_ctx *c)
 struct PhaseTimer {
     pibm_ctx *c;
     int phase;
+    hipStream_t s;
     hipEvent_t a = nullptr, b = nullptr;
-    PhaseTimer(pibm_ctx *ctx, int ph) : c(ctx), phase(ph) {
-        if (c->prof_on && (a = take_event(c)) && (b = take_event(c))) hipEventRecord(a, c->stream);
+    PhaseTimer(pibm_ctx *ctx, int ph, hipStream_t st) : c(ctx), phase(ph), s(st) {
+        if (c->prof_on && (a = take_event(c)) && (b = take_event(c))) (void)hipEventRecord(a, s);
     }
+    PhaseTimer(pibm_ctx *ctx, int ph) : PhaseTimer(ctx, ph, ctx->stream) {}
     ~PhaseTimer() {
         if (a && b) {
-            hipEventRecord(b, c->stream);
+            (void)hipEventRecord(b, s);
             c->ev_rec[phase].emplace_back(a, b);
         } else {
             if (a) c->ev_free.push_back(a);
@@ -687,18 +703,56 @@ struct PhaseTimer {
     }
 };
 
+int rec(pibm_ctx *c, hipEvent_t ev, hipStream_t s) { return hip_ok(c, hipEventRecord(ev, s)); }
+int wait(pibm_ctx *c, hipStream_t s, hipEvent_t ev) { return hip_ok(c, hipStreamWaitEvent(s, ev, 0)); }
+
+// One step: exchange, binning, lattice, DEM, in this order on the caller's
+// stream, or on two streams.  Binning reads only the particle state, so it runs
+// beside the exchange (markers or closure).  The DEM reads the particle state
+// and the exchange's reactions and writes the other particle buffer and the
+// contact history, none of which the lattice kernel touches, so it runs
+// beside the lattice kernel:
+//   stream: exchange --(mk)-- wait(bin) -- lattice -- wait(join)
+//   side:   wait(start) -- bin --(bin)-- wait(mk) -- DEM --(join)
+// Binning precedes the DEM on the side stream, so the particle buffer it
+// reads is overwritten only after it finished.
 template <int DIM, class SF>
 int step_impl(pibm_ctx *c, int n)
 {
-    for (int s = 0; s < n; ++s) {
+    if (!c->two) {
+        for (int k = 0; k < n; ++k) {
+            int st;
+            {
+                PhaseTimer t(c, PIBM_PHASE_MARKERS);
+                if ((st = c->closure ? launch_closure<DIM, SF>(c) : launch_markers<DIM, SF>(c, true))) return st;
+            }
+            { PhaseTimer t(c, PIBM_PHASE_BIN); if ((st = launch_bin(c, c->stream))) return st; }
+            { PhaseTimer t(c, PIBM_PHASE_LATTICE); if ((st = launch_lbm<DIM, SF, false>(c))) return st; }
+            { PhaseTimer t(c, PIBM_PHASE_DEM); if ((st = launch_dem(c, c->stream))) return st; }
+            c->cur ^= 1;
+            c->step++;
+        }
+        return PIBM_OK;
+    }
+    const bool parts = c->P.np > 0;
+    for (int k = 0; k < n; ++k) {
         int st;
+        if (parts) {
+            if ((st = rec(c, c->ev_start, c->stream)) || (st = wait(c, c->side, c->ev_start))) return st;
+            { PhaseTimer t(c, PIBM_PHASE_BIN, c->side); if ((st = launch_bin(c, c->side))) return st; }
+            if ((st = rec(c, c->ev_bin, c->side))) return st;
+        }
         {
             PhaseTimer t(c, PIBM_PHASE_MARKERS);
             if ((st = c->closure ? launch_closure<DIM, SF>(c) : launch_markers<DIM, SF>(c, true))) return st;
         }
-        { PhaseTimer t(c, PIBM_PHASE_BIN); if ((st = launch_bin(c))) return st; }
+        if (parts) {
+            if ((st = rec(c, c->ev_mk, c->stream)) || (st = wait(c, c->side, c->ev_mk))) return st;
+            { PhaseTimer t(c, PIBM_PHASE_DEM, c->side); if ((st = launch_dem(c, c->side))) return st; }
+            if ((st = rec(c, c->ev_join, c->side)) || (st = wait(c, c->stream, c->ev_bin))) return st;
+        }
         { PhaseTimer t(c, PIBM_PHASE_LATTICE); if ((st = launch_lbm<DIM, SF, false>(c))) return st; }
-        { PhaseTimer t(c, PIBM_PHASE_DEM); if ((st = launch_dem(c))) return st; }
+        if (parts && (st = wait(c, c->stream, c->ev_join))) return st;
         c->cur ^= 1;
         c->step++;
     }
@@ -710,7 +764,7 @@ int macro_impl(pibm_ctx *c)
 {
     int st;
     if ((st = c->closure ? launch_closure<DIM, SF>(c) : launch_markers<DIM, SF>(c, false))) return st;
-    if ((st = launch_bin(c))) return st;
+    if ((st = launch_bin(c, c->stream))) return st;
     return launch_lbm<DIM, SF, true>(c);
 }
 
@@ -874,6 +928,18 @@ int pibm_init(pibm_ctx **out, const pibm_params *p, const pibm_particle *pt, int
     c->ws = (char *)ws;
     c->ws_bytes = ws_bytes;
     c->cur = 0; c->pcur = 0; c->hcur = 0; c->step = 0; c->sticky = 0; c->device_lost = 0; c->cells_ok = 0;
+    c->two = c->P.np > 0 && (p->streams == 2 || (p->streams == 0 && c->P.N >= (1LL << 22)));
+    if (c->two) {   // the side stream and the fork/join events, on the device of the caller's stream
+        int dev = 0, cur = 0;
+        hipError_t e = hipStreamGetDevice(c->stream, &dev);
+        if (e == hipSuccess) e = hipGetDevice(&cur);
+        if (e == hipSuccess && dev != cur) e = hipSetDevice(dev);
+        if (e == hipSuccess) e = hipStreamCreateWithFlags(&c->side, hipStreamNonBlocking);
+        for (hipEvent_t *ev : {&c->ev_start, &c->ev_bin, &c->ev_mk, &c->ev_join})
+            if (e == hipSuccess) e = hipEventCreateWithFlags(ev, hipEventDisableTiming);
+        if (dev != cur) (void)hipSetDevice(cur);
+        if (e != hipSuccess) { delete c; return PIBM_EDEVICE; }
+    }
     // templates, marker offsets
     std::vector<double> tm((size_t)std::max(c->P.ntmpl_mk, 1LL) * 4, 0.0);
     std::vector<int> ts(c->P.tmpls.size() + 1, 0);

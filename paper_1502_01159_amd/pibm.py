@@ -46,6 +46,7 @@ class Params(ctypes.Structure):
         ("poisson", ctypes.c_double), ("mu_fric", ctypes.c_double), ("n_sub", ctypes.c_int),
         ("beta_p", ctypes.c_double), ("c_r", ctypes.c_double), ("skin", ctypes.c_double),
         ("interp_order", ctypes.c_int), ("lattice", ctypes.c_int), ("thermal_model", ctypes.c_int),
+        ("streams", ctypes.c_int),
     ]
 
 
@@ -154,6 +155,7 @@ def make_params(cfg: dict, storage: str = "f32") -> Params:
     p.interp_order = int(cfg.get("interp_order", 2))
     p.lattice = int(cfg.get("lattice", 19))
     p.thermal_model = int(cfg.get("thermal_model", 0))
+    p.streams = int(cfg.get("streams", 0))
     return p
 
 

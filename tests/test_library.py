@@ -74,6 +74,9 @@ def test_lattice_and_interpolation_options_validated(L):
     assert size(dict(cfg, thermal_model=1), "f64") > 0
     assert size(dict(cfg, thermal_model=1), "f16") == 0
     assert size(dict(cfg, thermal_model=2)) == 0
+    # one or two streams: same workspace, other values refused
+    assert size(dict(cfg, streams=1)) == size(dict(cfg, streams=2)) == n19
+    assert size(dict(cfg, streams=3)) == 0 and size(dict(cfg, streams=-1)) == 0
 
 
 def test_full_size_workspace_fits_hbm(L):
