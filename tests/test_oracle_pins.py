@@ -454,6 +454,27 @@ def test_fixed_hot_body_heats_fluid_and_drag_opposes_motion(oracle_mod):
     assert o.totals()[4] > 0
 
 
+@pytest.mark.parametrize("d,rho_r", [(4.0, 1.01), (0.5, 1.01), (1.0, 2.5)])
+def test_point_particle_first_step_relaxation(oracle_mod, d, rho_r):
+    """Eqs. (lbm7)-(lbm8), (lbm13) with A_p = pi d^2 / 4 (one point per
+    particle) and the DEM's m du = F dt: a point particle moving at U0
+    through fluid at rest (rho = 1, j = 0 at the point) feels
+    F = -2 A_p U0, so after one step U1 = U0 (1 - 2 A_p / m) with
+    m = rho_r pi d^3 / 6, i.e. the factor 1 - 3 / (rho_r d).  For d = h / 2
+    and rho_r = 1.01 (the paper's planted 3D case) the factor is -4.94: the
+    explicit exchange amplifies the slip every step."""
+    U0 = 0.01
+    cfg = base3d(nx=12, ny=12, nz=12, marker_mode=2)
+    P = np.array([prow((5.5, 5.5, 5.5), 0.5 * d, rho_r=rho_r, u=(U0, 0.0, 0.0))])
+    o = oracle_mod.Oracle(cfg, P)
+    o.step(1)
+    A = 0.25 * math.pi * d * d
+    r = o.reactions()[0]
+    assert abs(r[0] + 2.0 * A * U0) < 1e-15 and np.abs(r[1:6]).max() < 1e-15
+    factor = 1.0 - 3.0 / (rho_r * d)
+    assert abs(o.particles()[0, 3] - U0 * factor) < 1e-14
+
+
 # --------------------------------------------------------------------------- #
 # Symmetry (P10)                                                               #
 # --------------------------------------------------------------------------- #
