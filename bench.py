@@ -43,6 +43,12 @@ def source_hash() -> str:
     return h.hexdigest()[:16]
 
 
+def two_streams(nodes: int, particles: int) -> int:
+    """Streams the library's step uses with pibm_params.streams = 0: two from
+    2^22 nodes when there are particles, else one."""
+    return 2 if particles > 0 and nodes >= (1 << 22) else 1
+
+
 def read_traffic(workload: str, storage: str):
     """HBM bytes per launch of the lattice kernel from the committed rocprofv3
     counter summary, if it was taken on the current kernel source."""
@@ -282,7 +288,8 @@ def main() -> int:
         "dtype": args.storage,
         "data": "synthetic",
         "config": {"workload": WORKLOAD_TEXT[args.workload], "nodes": N, "particles": len(P),
-                   "markers": main_run["markers"], "storage": args.storage, "n_sub": cfg["n_sub"]},
+                   "markers": main_run["markers"], "storage": args.storage, "n_sub": cfg["n_sub"],
+                   "streams": two_streams(N, len(P))},
         "roofline": {
             "bound": "hbm",
             "kernel": "k_lbm (fused stream + PIBM spreading + forced BGK, f and g)",
@@ -296,6 +303,9 @@ def main() -> int:
         },
         "whole_step_hbm_frac": round(mlups * 1e6 * bytes_node / (HBM_PEAK_GBS * 1e9), 4),
         "phase_ms_per_step": phases,
+        "phase_note": ("two streams: binning runs beside the markers and the DEM beside the lattice, so the phase "
+                       "spans overlap and sum to more than ms_per_step" if two_streams(N, len(P)) == 2 else
+                       "one stream: the phases run one after another"),
         "variants": variants,
     }
     if "mlp" in [v for v in args.variants.split(",") if v]:

@@ -1228,7 +1228,7 @@ int pibm_destroy(pibm_ctx *c)
     if (!c) return PIBM_OK;
     for (int ph = 0; ph < PIBM_NPHASE; ++ph)
         for (auto &pr : c->ev_rec[ph]) c->ev_free.insert(c->ev_free.end(), {pr.first, pr.second});
-    for (hipEvent_t e : c->ev_free) hipEventDestroy(e);
+    for (hipEvent_t e : c->ev_free) (void)hipEventDestroy(e);
     delete c;
     return PIBM_OK;
 }

@@ -143,6 +143,36 @@ def test_closure_step_applies_network_outputs(gpu, oracle_mod):
     sim.close()
 
 
+def test_closure_two_streams_match_one_stream(gpu):
+    """With the network as the closure, binning on a second stream beside the
+    closure's kernels and the DEM beside the lattice give the same bits as one
+    stream."""
+    cfg, P = W.workload("c3_small")
+    cfg = W.with_overrides(cfg, marker_mode=2)
+    P = sub_grid(P)
+    mlp = gpu.Mlp(seed=5, max_batch=64)
+    probe = gpu.Simulation(cfg, P, storage="f32")
+    x, _ = probe.features()
+    probe.close()
+    mu = x.mean(0).astype(np.float32)
+    sd = (x.std(0) + 0.1).astype(np.float32)
+    norm = np.concatenate([mu, sd, np.array([0.5, -0.2, 0.1, 0.3], np.float32), np.array([2.0, 1.0, 1.5, 0.5], np.float32)])
+    out = []
+    for streams in (1, 2):
+        sim = gpu.Simulation(dict(cfg, streams=streams), P, storage="f32")
+        sim.set_closure(mlp, norm)
+        sim.step(5)
+        assert sim.sync() == gpu.OK
+        f, g = sim.populations()
+        q, r = sim.particles()
+        out.append((f, g, q, r))
+        sim.set_closure(None)
+        sim.close()
+    mlp.close()
+    for a, b in zip(*out):
+        assert np.array_equal(a, b)
+
+
 def test_learned_closure_beats_point_exchange(gpu):
     """What the network gains over the method without it.  Resolved runs of
     fixed hot spheres in a driven periodic box give samples; the network is
