@@ -172,6 +172,26 @@ def test_workloads_f32_1000_steps(gpu, oracle_mod, name, steps):
     assert dx <= 1e-4
 
 
+@pytest.mark.parametrize("storage,steps,bound", [("f64", 3, 1e-9), ("f32", 4, 1e-5)])
+def test_full_size_c3_every_node(gpu, oracle_mod, storage, steps, bound):
+    """The benchmark's default workload itself (256 x 256 x 512, 2000 spheres,
+    the two-stream step) against the oracle on every node and every particle
+    after a few steps: FP64 storage to the FP64 bar, FP32 to the FP32 bar."""
+    cfg, P = W.workload("c3")
+    sim, ref = run_pair(gpu, oracle_mod, cfg, P, steps, storage)
+    e = field_errors(sim.fields(), ref.fields())
+    print("c3", storage, steps, "steps: field errors", e)
+    assert max(e.values()) <= bound, e
+    q, fth = sim.particles()
+    rq = ref.particles()
+    dx = np.abs(q[:, :3] - rq[:, :3]).max()
+    print("c3", storage, "max position error", dx)
+    assert dx <= (1e-10 if storage == "f64" else 1e-4)
+    if storage == "f64":
+        reactions_close(fth, ref.reactions(), 1e-9, R=P[:, 9].max())
+    sim.close()
+
+
 @pytest.mark.parametrize("storage,bound", [("f16", 1e-3), ("bf16", 1e-2)])
 def test_16bit_deviation_storage_error(gpu, oracle_mod, storage, bound):
     """FP16 / BF16 deviation storage collided in FP32: per-field error against
