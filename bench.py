@@ -63,7 +63,10 @@ def read_traffic(workload: str, storage: str):
     return float(b.group(1))
 
 
-def time_gpu(cfg, P, storage, steps, warmup, profile):
+def time_gpu(cfg, P, storage, steps, warmup, phase_steps=0):
+    """Times `steps` steps with events around the lattice kernel only (each
+    timed phase adds an event pair to the stream); then, untimed, reads every
+    phase's time over `phase_steps` further steps."""
     import torch
 
     from paper_1502_01159_amd import pibm
@@ -72,9 +75,8 @@ def time_gpu(cfg, P, storage, steps, warmup, profile):
     sim.step(warmup)
     if sim.sync() != pibm.OK:
         raise RuntimeError(f"watchdog during warm-up ({storage})")
-    if profile:
-        sim.profile(True)
-        sim.profile_read()
+    sim.profile(True, phases=["lattice"])
+    sim.profile_read()
     torch.cuda.synchronize()
     ev0 = torch.cuda.Event(enable_timing=True)
     ev1 = torch.cuda.Event(enable_timing=True)
@@ -88,8 +90,17 @@ def time_gpu(cfg, P, storage, steps, warmup, profile):
     if st != pibm.OK:
         raise RuntimeError(f"watchdog during the timed steps ({storage}): {pibm.strerror(st)}")
     ms = ev0.elapsed_time(ev1)
-    prof = sim.profile_read() if profile else None
-    out = dict(ms=ms, wall_s=wall, N=sim.N, Q=sim.Q, Qg=sim.Qg, markers=sim.num_markers, prof=prof)
+    prof = sim.profile_read()
+    all_prof = None
+    if phase_steps:
+        sim.profile(True)
+        sim.step(phase_steps)
+        all_prof = sim.profile_read()
+        sim.profile(False)
+        if sim.sync() != pibm.OK:
+            raise RuntimeError(f"watchdog during the phase run ({storage})")
+    out = dict(ms=ms, wall_s=wall, N=sim.N, Q=sim.Q, Qg=sim.Qg, markers=sim.num_markers, prof=prof,
+               all_prof=all_prof)
     sim.close()
     del sim
     torch.cuda.empty_cache()
@@ -175,17 +186,17 @@ def mlp_variant(steps):
     sim.step(5)
     if sim.sync() != pibm.OK:
         raise RuntimeError("coarse closure run failed in warm-up")
-    sim.profile(True)
-    sim.profile_read()
     torch.cuda.synchronize()
     ev0.record()
     sim.step(steps)
     ev1.record()
     torch.cuda.synchronize()
     ms_c = ev0.elapsed_time(ev1) / steps
+    sim.profile(True)                     # phase times from further, untimed steps
+    sim.step(20)
+    prof = {k: round(v[0] / max(v[1], 1), 4) for k, v in sim.profile_read().items()}
     if sim.sync() != pibm.OK:
         raise RuntimeError("coarse closure run failed")
-    prof = {k: round(v[0] / max(v[1], 1), 4) for k, v in sim.profile_read().items()}
     Nc, Nf = sim.N, cfg["nx"] * cfg["ny"] * cfg["nz"]
     out["coarse_step"] = dict(workload=f"fixed hot spheres, {cc['nx']}^3 coarse lattice (256^3 resolved / 4), "
                                        f"{len(P)} one-point particles, network closure",
@@ -242,7 +253,7 @@ def main() -> int:
     cfg, P = W.workload(args.workload)
     if args.empty:
         P = P[:0]
-    main_run = time_gpu(cfg, P, args.storage, args.steps, args.warmup, profile=True)
+    main_run = time_gpu(cfg, P, args.storage, args.steps, args.warmup, phase_steps=20)
     N, Q, Qg = main_run["N"], main_run["Q"], main_run["Qg"]
     ms_step = main_run["ms"] / args.steps
     mlups = N * args.steps / (main_run["ms"] * 1e-3) / 1e6
@@ -252,7 +263,7 @@ def main() -> int:
     lat_avg_s = lat_ms * 1e-3 / max(lat_n, 1)
     algo_bytes = N * bytes_node                       # one launch updates every node once
     achieved = algo_bytes / lat_avg_s / 1e9
-    phases = {k: round(v[0] / max(v[1], 1), 4) for k, v in main_run["prof"].items()}
+    phases = {k: round(v[0] / max(v[1], 1), 4) for k, v in main_run["all_prof"].items()}
 
     variants = {}
     for st in [s for s in args.variants.split(",") if s and s != args.storage and s != "mlp"]:
@@ -264,7 +275,7 @@ def main() -> int:
             vcfg, vst = W.with_overrides(cfg, lattice=15, thermal_model=1), "f32"
         else:
             vcfg, vst = cfg, st
-        r = time_gpu(vcfg, P, vst, max(args.steps // 2, 10), args.warmup, profile=True)
+        r = time_gpu(vcfg, P, vst, max(args.steps // 2, 10), args.warmup)
         lms, ln = r["prof"]["lattice"]
         n_steps = max(args.steps // 2, 10)
         b = 2 * (r["Q"] + r["Qg"]) * STORAGE_BYTES[vst]
@@ -303,9 +314,11 @@ def main() -> int:
         },
         "whole_step_hbm_frac": round(mlups * 1e6 * bytes_node / (HBM_PEAK_GBS * 1e9), 4),
         "phase_ms_per_step": phases,
-        "phase_note": ("two streams: binning runs beside the markers and the DEM beside the lattice, so the phase "
-                       "spans overlap and sum to more than ms_per_step" if two_streams(N, len(P)) == 2 else
-                       "one stream: the phases run one after another"),
+        "phase_note": ("phase times from 20 further steps with events around every phase (the timed steps carry "
+                       "events around the lattice kernel only); " +
+                       ("two streams: binning runs beside the markers and the DEM beside the lattice, so the phase "
+                        "spans overlap and sum to more than ms_per_step" if two_streams(N, len(P)) == 2 else
+                        "one stream: the phases run one after another")),
         "variants": variants,
     }
     if "mlp" in [v for v in args.variants.split(",") if v]:

@@ -191,16 +191,21 @@ int pibm_save(pibm_ctx *ctx, void *host_buf, size_t cap, size_t *used);
 int pibm_load(pibm_ctx *ctx, const void *host_buf, size_t n);
 
 /* Phase profiling.  While enabled, pibm_step records a pair of HIP events
- * on the context's stream around each phase of every step:
+ * around each timed phase of every step, on the stream that runs the phase:
  *   PIBM_PHASE_MARKERS  Lagrangian points: interpolation, exchange, reactions;
  *   PIBM_PHASE_BIN      particle -> lattice-tile binning;
  *   PIBM_PHASE_LATTICE  the fused stream / spreading / collision kernel;
  *   PIBM_PHASE_DEM      neighbour lists and the DEM sub-steps.
  * pibm_profile_read synchronises, returns per phase the summed elapsed
  * milliseconds ms[PIBM_NPHASE] and the number of timed phase executions
- * count[PIBM_NPHASE] since the previous read, and resets them. */
+ * count[PIBM_NPHASE] since the previous read, and resets them.  Each event
+ * pair costs the stream a few microseconds, so pibm_profile_phases times only
+ * the phases whose bit (1 << PIBM_PHASE_*) is set in phase_mask (0: none;
+ * bits beyond the phases: PIBM_EINVAL); pibm_profile(ctx, enable) times all
+ * phases or none. */
 enum { PIBM_PHASE_MARKERS = 0, PIBM_PHASE_BIN = 1, PIBM_PHASE_LATTICE = 2, PIBM_PHASE_DEM = 3, PIBM_NPHASE = 4 };
 int pibm_profile(pibm_ctx *ctx, int enable);
+int pibm_profile_phases(pibm_ctx *ctx, unsigned phase_mask);
 int pibm_profile_read(pibm_ctx *ctx, double *ms, long long *count);
 
 /* Release the context (not the caller's workspace or stream). */

@@ -423,7 +423,7 @@ struct pibm_ctx {
     int device_lost;
     pibm_mlp *closure = nullptr;   // learned closure in the one-point mode (not owned)
     // phase profiling: pairs of events recorded around each phase's launches
-    int prof_on = 0;
+    unsigned prof_mask = 0;        // phases timed (bit 1 << PIBM_PHASE_*)
     std::vector<hipEvent_t> ev_free;
     std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_rec[PIBM_NPHASE];
     void *r(int reg) const { return ws + P.off[reg]; }
@@ -689,7 +689,7 @@ struct PhaseTimer {
     hipStream_t s;
     hipEvent_t a = nullptr, b = nullptr;
     PhaseTimer(pibm_ctx *ctx, int ph, hipStream_t st) : c(ctx), phase(ph), s(st) {
-        if (c->prof_on && (a = take_event(c)) && (b = take_event(c))) (void)hipEventRecord(a, s);
+        if (((c->prof_mask >> ph) & 1u) && (a = take_event(c)) && (b = take_event(c))) (void)hipEventRecord(a, s);
     }
     PhaseTimer(pibm_ctx *ctx, int ph) : PhaseTimer(ctx, ph, ctx->stream) {}
     ~PhaseTimer() {
@@ -1198,7 +1198,14 @@ int pibm_load(pibm_ctx *c, const void *buf, size_t n)
 int pibm_profile(pibm_ctx *c, int enable)
 {
     if (!c) return PIBM_EINVAL;
-    c->prof_on = enable ? 1 : 0;
+    c->prof_mask = enable ? (1u << PIBM_NPHASE) - 1u : 0u;
+    return PIBM_OK;
+}
+
+int pibm_profile_phases(pibm_ctx *c, unsigned phase_mask)
+{
+    if (!c || (phase_mask >> PIBM_NPHASE)) return PIBM_EINVAL;
+    c->prof_mask = phase_mask;
     return PIBM_OK;
 }
 

@@ -24,7 +24,7 @@ EXPORTS = [
     "pibm_workspace_bytes", "pibm_init", "pibm_step", "pibm_sync", "pibm_particles", "pibm_set_particles",
     "pibm_fields", "pibm_get_populations", "pibm_set_populations", "pibm_num_nodes", "pibm_num_markers",
     "pibm_step_count", "pibm_derived", "pibm_save", "pibm_load", "pibm_destroy", "pibm_strerror",
-    "pibm_profile", "pibm_profile_read",
+    "pibm_profile", "pibm_profile_phases", "pibm_profile_read",
     "pibm_mlp_workspace_bytes", "pibm_mlp_create", "pibm_mlp_set_params", "pibm_mlp_get_params",
     "pibm_mlp_forward", "pibm_mlp_grads", "pibm_mlp_train_step", "pibm_mlp_destroy",
     "pibm_features", "pibm_set_closure",
@@ -94,6 +94,7 @@ def lib():
         L.pibm_load.argtypes = [vp, vp, sz]
         L.pibm_destroy.argtypes = [vp]
         L.pibm_profile.argtypes = [vp, ctypes.c_int]
+        L.pibm_profile_phases.argtypes = [vp, ctypes.c_uint]
         L.pibm_profile_read.argtypes = [vp, dp, ctypes.POINTER(ctypes.c_longlong)]
         L.pibm_strerror.restype = ctypes.c_char_p
         L.pibm_strerror.argtypes = [ctypes.c_int]
@@ -312,8 +313,16 @@ class Simulation:
         g = np.ascontiguousarray(g, dtype=np.float64).reshape(self.Qg, self.N)
         self._check(lib().pibm_set_populations(self._h, _dp(f), _dp(g)), "pibm_set_populations")
 
-    def profile(self, enable: bool = True):
-        self._check(lib().pibm_profile(self._h, int(bool(enable))), "pibm_profile")
+    def profile(self, enable: bool = True, phases=None):
+        """Time every phase (or none); `phases` (names from PHASES) times only
+        those, since each timed phase adds a pair of events to the stream."""
+        if phases is None:
+            self._check(lib().pibm_profile(self._h, int(bool(enable))), "pibm_profile")
+            return
+        mask = 0
+        for p in phases:
+            mask |= 1 << PHASES.index(p)
+        self._check(lib().pibm_profile_phases(self._h, mask if enable else 0), "pibm_profile_phases")
 
     def profile_read(self) -> dict:
         """{phase: (total ms, timed executions)} since the previous read."""

@@ -273,6 +273,27 @@ def test_two_streams_match_one_stream(gpu, case, storage):
         assert np.array_equal(a, b)
 
 
+def test_profile_phases(gpu):
+    """Phase profiling times only the phases in the mask; the full mask times
+    all four; bits beyond the phases are refused."""
+    cfg, P = W.workload("c2_small")
+    s = gpu.Simulation(cfg, P, storage="f32")
+    s.profile(True, phases=["lattice"])
+    s.step(3)
+    r = s.profile_read()
+    assert r["lattice"][1] == 3 and r["lattice"][0] > 0
+    assert r["markers"][1] == r["bin"][1] == r["dem"][1] == 0
+    s.profile(True)
+    s.step(2)
+    r = s.profile_read()
+    assert all(r[p][1] == 2 for p in gpu.PHASES)
+    s.profile(False)
+    s.step(1)
+    assert all(v[1] == 0 for v in s.profile_read().values())
+    assert gpu.lib().pibm_profile_phases(s._h, 1 << len(gpu.PHASES)) == gpu.EINVAL
+    s.close()
+
+
 def test_rest_state_exact_in_f32(gpu):
     """P1 on the GPU: deviation storage keeps the rest state exactly."""
     cfg = dict(dim=3, nx=70, ny=9, nz=6, periodic=[0, 1, 0], T_wall=[0.5] * 6, T_init=0.5, T_ref=0.5,
