@@ -1536,7 +1536,8 @@ __global__ __launch_bounds__(BIN_THREADS) void k_bin(BinArgs a)
     const DevParticle P = a.part[p];
     // a non-finite or runaway centre would give meaningless loop bounds
     bool finite = true;
-    for (int d = 0; d < a.dim; ++d) finite = finite && fabs(P.x[d]) < 1.0e8;
+#pragma unroll
+    for (int d = 0; d < 3; ++d) finite = finite && (d >= a.dim || fabs(P.x[d]) < 1.0e8);   // constant indices
     if (!finite) {
         if (!FILL && lane == 0) atomicOr(a.err, ERR_DOMAIN);
         return;
@@ -1865,9 +1866,13 @@ __device__ __forceinline__ void dem_particle(const DemArgs &a, int i)
         for (int c = 0; c < 3; ++c) { Fc[c] += F[c]; Tc[c] += T[c]; }
         record(j, xn);
     }
+    // walls; loops over axes run to 3 with a guard so that every index is a
+    // constant and the particle records stay in registers
     const int nn3[3] = {a.nx, a.ny, a.nz};
-    for (int ax = 0; ax < dim; ++ax) {
-        if (a.per[ax]) continue;
+#pragma unroll
+    for (int ax = 0; ax < 3; ++ax) {
+        if (ax >= dim || a.per[ax]) continue;
+#pragma unroll
         for (int side = 0; side < 2; ++side) {
             const double gap = side == 0 ? P.x[ax] + 0.5 : (nn3[ax] - 0.5) - P.x[ax];
             const double delta = P.R - gap;
@@ -1896,10 +1901,12 @@ __device__ __forceinline__ void dem_particle(const DemArgs &a, int i)
         const double I = dim == 2 ? 0.5 * m * P.R * P.R : 0.4 * m * P.R * P.R;
         double rho_p = P.rho_r;
         if (P.flags & 2) rho_p = P.rho_r * (1.0 - a.beta_p * (P.T - a.Tref));
-        double gv[3] = {0, 0, 0};
-        gv[dim - 1] = -a.gravity * (1.0 - 1.0 / rho_p);
-        for (int c = 0; c < dim; ++c) {
-            O.u[c] = P.u[c] + a.dts * ((Rh.F[c] + Fc[c]) / m + gv[c]);
+        const double gup = -a.gravity * (1.0 - 1.0 / rho_p);     // along the last axis
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            if (c >= dim) continue;
+            const double gv = c == dim - 1 ? gup : 0.0;
+            O.u[c] = P.u[c] + a.dts * ((Rh.F[c] + Fc[c]) / m + gv);
             O.x[c] = P.x[c] + a.dts * O.u[c];
         }
         if (dim == 2) {
@@ -1924,7 +1931,9 @@ __device__ __forceinline__ void dem_particle(const DemArgs &a, int i)
     min_image(a, xr, O.x, dd);
     int e = 0;
     if (!(dd[0] * dd[0] + dd[1] * dd[1] + dd[2] * dd[2] <= 0.25 * a.skin * a.skin)) e |= ERR_STALE;
-    for (int c = 0; c < dim; ++c) {
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        if (c >= dim) continue;
         if (!a.per[c] && !(O.x[c] > -0.5 && O.x[c] < nn3[c] - 0.5)) e |= ERR_DOMAIN;
         if (!(fabs(O.x[c]) < 1.0e8) || !(fabs(O.u[c]) < 1.0e8)) e |= ERR_DOMAIN;
     }
