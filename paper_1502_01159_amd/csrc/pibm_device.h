@@ -1269,13 +1269,16 @@ __global__ __launch_bounds__(FEAT_THREADS) void k_features(FeatArgs<typename SF:
             if (d2 < rphi * rphi)
                 vol += DIM == 3 ? (4.0 / 3.0) * M_PI * Q.R * Q.R * Q.R : M_PI * Q.R * Q.R;
             if (jn == p) return;
-            if (d2 < bd[NN - 1] || (d2 == bd[NN - 1] && jn < bi[NN - 1])) {   // sorted insert
-                int q = NN - 1;
-                while (q > 0 && (d2 < bd[q - 1] || (d2 == bd[q - 1] && jn < bi[q - 1]))) {
-                    bd[q] = bd[q - 1]; bi[q] = bi[q - 1];
-                    --q;
-                }
-                bd[q] = d2; bi[q] = jn;
+            if (d2 < bd[NN - 1] || (d2 == bd[NN - 1] && jn < bi[NN - 1])) {
+                // sorted insert: replace the last entry and move it up past every
+                // larger one (constant indices keep the list in registers)
+                bd[NN - 1] = d2; bi[NN - 1] = jn;
+#pragma unroll
+                for (int q = NN - 1; q > 0; --q)
+                    if (bd[q] < bd[q - 1] || (bd[q] == bd[q - 1] && bi[q] < bi[q - 1])) {
+                        const double td = bd[q]; bd[q] = bd[q - 1]; bd[q - 1] = td;
+                        const int ti = bi[q]; bi[q] = bi[q - 1]; bi[q - 1] = ti;
+                    }
             }
         };
         // nearest NN of the lanes' sorted lists: NN rounds of a wave minimum over
@@ -1283,6 +1286,7 @@ __global__ __launch_bounds__(FEAT_THREADS) void k_features(FeatArgs<typename SF:
         double nd[6];
         int ni[6];
         auto select = [&]() {
+#pragma unroll
             for (int r = 0; r < NN; ++r) {
                 double md = bd[0];
                 int mi = bi[0];
