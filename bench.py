@@ -241,6 +241,8 @@ def main() -> int:
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--empty", action="store_true", help="analysis: the same lattice without particles")
     ap.add_argument("--no-copy-probe", action="store_true")
+    ap.add_argument("--streams", type=int, default=0, choices=(0, 1, 2),
+                    help="pibm_params.streams: 0 automatic, 1 one stream, 2 two streams")
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
@@ -251,6 +253,8 @@ def main() -> int:
     from paper_1502_01159_amd import workloads as W
 
     cfg, P = W.workload(args.workload)
+    if args.streams:
+        cfg = W.with_overrides(cfg, streams=args.streams)
     if args.empty:
         P = P[:0]
     main_run = time_gpu(cfg, P, args.storage, args.steps, args.warmup, phase_steps=20)
@@ -300,7 +304,7 @@ def main() -> int:
         "data": "synthetic",
         "config": {"workload": WORKLOAD_TEXT[args.workload], "nodes": N, "particles": len(P),
                    "markers": main_run["markers"], "storage": args.storage, "n_sub": cfg["n_sub"],
-                   "streams": two_streams(N, len(P))},
+                   "streams": args.streams or two_streams(N, len(P))},
         "roofline": {
             "bound": "hbm",
             "kernel": "k_lbm (fused stream + PIBM spreading + forced BGK, f and g)",
@@ -317,7 +321,8 @@ def main() -> int:
         "phase_note": ("phase times from 20 further steps with events around every phase (the timed steps carry "
                        "events around the lattice kernel only); " +
                        ("two streams: binning runs beside the markers and the DEM beside the lattice, so the phase "
-                        "spans overlap and sum to more than ms_per_step" if two_streams(N, len(P)) == 2 else
+                        "spans overlap and sum to more than ms_per_step"
+                        if (args.streams or two_streams(N, len(P))) == 2 else
                         "one stream: the phases run one after another")),
         "variants": variants,
     }
