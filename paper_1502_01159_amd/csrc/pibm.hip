@@ -713,7 +713,7 @@ int wait(pibm_ctx *c, hipStream_t s, hipEvent_t ev) { return hip_ok(c, hipStream
 // contact history, none of which the lattice kernel touches, so it runs
 // beside the lattice kernel:
 //   stream: exchange --(mk)-- wait(bin) -- lattice -- wait(join)
-//   side:   wait(start) -- bin --(bin)-- wait(mk) -- DEM --(join)
+//   side:   wait(start) -- bin --(bin)-- wait(mk) -- DEM, next cell list --(join)
 // Binning precedes the DEM on the side stream, so the particle buffer it
 // reads is overwritten only after it finished.
 template <int DIM, class SF>
@@ -748,7 +748,13 @@ int step_impl(pibm_ctx *c, int n)
         }
         if (parts) {
             if ((st = rec(c, c->ev_mk, c->stream)) || (st = wait(c, c->side, c->ev_mk))) return st;
-            { PhaseTimer t(c, PIBM_PHASE_DEM, c->side); if ((st = launch_dem(c, c->side))) return st; }
+            {
+                PhaseTimer t(c, PIBM_PHASE_DEM, c->side);
+                if ((st = launch_dem(c, c->side))) return st;
+                // the next step's cell list from the new state, beside the lattice kernel
+                // (nothing reads the list until the next exchange)
+                if ((st = build_cells(c, c->side))) return st;
+            }
             if ((st = rec(c, c->ev_join, c->side)) || (st = wait(c, c->stream, c->ev_bin))) return st;
         }
         { PhaseTimer t(c, PIBM_PHASE_LATTICE); if ((st = launch_lbm<DIM, SF, false>(c))) return st; }
