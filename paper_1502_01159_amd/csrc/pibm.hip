@@ -29,7 +29,7 @@ size_t up(size_t v) { return (v + ALIGN - 1) / ALIGN * ALIGN; }
 enum Region {
     R_FA, R_GA, R_FB, R_GB, R_PART0, R_PART1, R_REACT, R_TMPL, R_TMPL_START, R_TMPL_REXT, R_MK_START, R_MK,
     R_TP_START, R_TP_BOX, R_GP_START, R_GP_BASE,
-    R_TCOUNT, R_TSTART, R_TFILL, R_TITEMS, R_CCOUNT, R_CSTART, R_CFILL, R_CITEMS, R_NBR, R_NBRN, R_XREF,
+    R_TCOUNT, R_TSTART, R_TFILL, R_TITEMS, R_TCOUNT1, R_TSTART1, R_TFILL1, R_TITEMS1, R_CCOUNT, R_CSTART, R_CFILL, R_CITEMS, R_NBR, R_NBRN, R_XREF,
     R_HID0, R_HXI0, R_HN0, R_HID1, R_HXI1, R_HN1, R_FEAT, R_TARG, R_AUX, R_XBF, R_YMLP, R_NORM, R_CNTR, R_ERR, R_COUNT
 };
 
@@ -309,6 +309,8 @@ int make_plan(const pibm_params *p, const pibm_particle *pt, int np, Plan &P)
     sz[R_TSTART] = (size_t)(P.ntiles + 1) * sizeof(int);
     sz[R_TFILL] = (size_t)P.ntiles * sizeof(int);
     sz[R_TITEMS] = std::max(P.tile_cap, 1LL) * sizeof(int);
+    // a second set of tile lists: the two-stream step bins the next step into it
+    sz[R_TCOUNT1] = sz[R_TCOUNT]; sz[R_TSTART1] = sz[R_TSTART]; sz[R_TFILL1] = sz[R_TFILL]; sz[R_TITEMS1] = sz[R_TITEMS];
     sz[R_CCOUNT] = (size_t)P.ncells * sizeof(int);
     sz[R_CSTART] = (size_t)(P.ncells + 1) * sizeof(int);
     sz[R_CFILL] = (size_t)P.ncells * sizeof(int);
@@ -418,6 +420,8 @@ struct pibm_ctx {
     int pcur;       // particle buffer holding the current state
     int hcur;       // contact-history buffer holding the current state
     int cells_ok;   // the cell list was built from the current particle state
+    int tcur = 0;   // tile-list set the lattice kernel reads (0: R_TCOUNT.., 1: R_TCOUNT1..)
+    int tiles_next = 0;   // the other set holds the lists of the current particle state
     long long step;
     int sticky;
     int device_lost;
@@ -456,9 +460,9 @@ template <class T> LbmArgs<T> lbm_args(const pibm_ctx *c)
     a.gA = c->r(src ? R_GB : R_GA);
     a.fB = c->r(src ? R_FA : R_FB);
     a.gB = c->r(src ? R_GA : R_GB);
-    a.tile_start = (const int *)c->r(R_TSTART);
-    a.tile_count = (const int *)c->r(R_TCOUNT);
-    a.tile_items = (const int *)c->r(R_TITEMS);
+    a.tile_start = (const int *)c->r(c->tcur ? R_TSTART1 : R_TSTART);
+    a.tile_count = (const int *)c->r(c->tcur ? R_TCOUNT1 : R_TCOUNT);
+    a.tile_items = (const int *)c->r(c->tcur ? R_TITEMS1 : R_TITEMS);
     a.gp_start = (const int *)c->r(R_GP_START);
     a.mk = (const MarkerRec<T> *)c->r(R_MK);
     a.err = (int *)c->r(R_ERR);
@@ -547,7 +551,7 @@ int launch_closure(pibm_ctx *c)
     return hip_ok(c, hipGetLastError());
 }
 
-BinArgs bin_args(pibm_ctx *c)
+BinArgs bin_args(pibm_ctx *c, int set)
 {
     BinArgs b{};
     b.dim = c->p.dim; b.nx = c->p.nx; b.ny = c->p.ny; b.nz = c->p.nz;
@@ -560,18 +564,19 @@ BinArgs bin_args(pibm_ctx *c)
     b.tp_box = (const double *)c->r(R_TP_BOX);
     b.gp_base = (const int *)c->r(R_GP_BASE);
     b.cap = c->P.tile_cap;
-    b.tile_count = (int *)c->r(R_TCOUNT);
-    b.tile_start = (int *)c->r(R_TSTART);
-    b.tile_fill = (int *)c->r(R_TFILL);
-    b.tile_items = (int *)c->r(R_TITEMS);
+    b.tile_count = (int *)c->r(set ? R_TCOUNT1 : R_TCOUNT);
+    b.tile_start = (int *)c->r(set ? R_TSTART1 : R_TSTART);
+    b.tile_fill = (int *)c->r(set ? R_TFILL1 : R_TFILL);
+    b.tile_items = (int *)c->r(set ? R_TITEMS1 : R_TITEMS);
     b.err = (int *)c->r(R_ERR);
     return b;
 }
 
-int launch_bin(pibm_ctx *c, hipStream_t s)
+// Tile lists of the current particle state into set `set`.
+int launch_bin(pibm_ctx *c, hipStream_t s, int set)
 {
     if (c->P.np == 0) return PIBM_OK;
-    BinArgs b = bin_args(c);
+    BinArgs b = bin_args(c, set);
     const int nt = c->P.ntiles;
     int *cntr = (int *)c->r(R_CNTR);
     hipLaunchKernelGGL(k_zero2, dim3(std::min(1024, (nt + 256) / 256)), dim3(256), 0, s, b.tile_count, (long long)nt,
@@ -712,8 +717,10 @@ int wait(pibm_ctx *c, hipStream_t s, hipEvent_t ev) { return hip_ok(c, hipStream
 // and the exchange's reactions and writes the other particle buffer and the
 // contact history, none of which the lattice kernel touches, so it runs
 // beside the lattice kernel:
-//   stream: exchange --(mk)-- wait(bin) -- lattice -- wait(join)
-//   side:   wait(start) -- bin --(bin)-- wait(mk) -- DEM, next cell list --(join)
+//   stream: exchange --(mk)-- [wait(bin)] -- lattice -- wait(join)
+//   side:   [wait(start) -- bin --(bin)--] wait(mk) -- DEM, next cell list, next bin --(join)
+// From the second step on, the bracketed binning is skipped: the previous
+// step binned into the idle tile-list set beside its lattice kernel.
 // Binning precedes the DEM on the side stream, so the particle buffer it
 // reads is overwritten only after it finished.
 template <int DIM, class SF>
@@ -726,7 +733,7 @@ int step_impl(pibm_ctx *c, int n)
                 PhaseTimer t(c, PIBM_PHASE_MARKERS);
                 if ((st = c->closure ? launch_closure<DIM, SF>(c) : launch_markers<DIM, SF>(c, true))) return st;
             }
-            { PhaseTimer t(c, PIBM_PHASE_BIN); if ((st = launch_bin(c, c->stream))) return st; }
+            { PhaseTimer t(c, PIBM_PHASE_BIN); if ((st = launch_bin(c, c->stream, c->tcur))) return st; }
             { PhaseTimer t(c, PIBM_PHASE_LATTICE); if ((st = launch_lbm<DIM, SF, false>(c))) return st; }
             { PhaseTimer t(c, PIBM_PHASE_DEM); if ((st = launch_dem(c, c->stream))) return st; }
             c->cur ^= 1;
@@ -737,9 +744,12 @@ int step_impl(pibm_ctx *c, int n)
     const bool parts = c->P.np > 0;
     for (int k = 0; k < n; ++k) {
         int st;
-        if (parts) {
+        // the previous step binned this one into the idle set, beside its lattice kernel
+        const bool binned = parts && c->tiles_next;
+        if (binned) { c->tcur ^= 1; c->tiles_next = 0; }
+        if (parts && !binned) {
             if ((st = rec(c, c->ev_start, c->stream)) || (st = wait(c, c->side, c->ev_start))) return st;
-            { PhaseTimer t(c, PIBM_PHASE_BIN, c->side); if ((st = launch_bin(c, c->side))) return st; }
+            { PhaseTimer t(c, PIBM_PHASE_BIN, c->side); if ((st = launch_bin(c, c->side, c->tcur))) return st; }
             if ((st = rec(c, c->ev_bin, c->side))) return st;
         }
         {
@@ -755,7 +765,12 @@ int step_impl(pibm_ctx *c, int n)
                 // (nothing reads the list until the next exchange)
                 if ((st = build_cells(c, c->side))) return st;
             }
-            if ((st = rec(c, c->ev_join, c->side)) || (st = wait(c, c->stream, c->ev_bin))) return st;
+            // the next step's tile lists into the idle set (its last reader, the
+            // previous lattice kernel, finished before this exchange)
+            { PhaseTimer t(c, PIBM_PHASE_BIN, c->side); if ((st = launch_bin(c, c->side, c->tcur ^ 1))) return st; }
+            c->tiles_next = 1;
+            if ((st = rec(c, c->ev_join, c->side))) return st;
+            if (!binned && (st = wait(c, c->stream, c->ev_bin))) return st;
         }
         { PhaseTimer t(c, PIBM_PHASE_LATTICE); if ((st = launch_lbm<DIM, SF, false>(c))) return st; }
         if (parts && (st = wait(c, c->stream, c->ev_join))) return st;
@@ -770,7 +785,8 @@ int macro_impl(pibm_ctx *c)
 {
     int st;
     if ((st = c->closure ? launch_closure<DIM, SF>(c) : launch_markers<DIM, SF>(c, false))) return st;
-    if ((st = launch_bin(c, c->stream))) return st;
+    c->tiles_next = 0;             // rebinning here; the next step bins again
+    if ((st = launch_bin(c, c->stream, c->tcur))) return st;
     return launch_lbm<DIM, SF, true>(c);
 }
 
@@ -879,6 +895,7 @@ int upload_particles(pibm_ctx *c, const pibm_particle *pt, int n)
     std::vector<DevParticle> dp(std::max(n, 1));
     for (int i = 0; i < n; ++i) dp[i] = to_dev(pt[i], c->P.ptmpl[i]);
     c->cells_ok = 0;
+    c->tiles_next = 0;
     if (n == 0) return PIBM_OK;
     hipError_t e = hipMemcpyAsync(c->r(c->pcur ? R_PART1 : R_PART0), dp.data(), sizeof(DevParticle) * n,
                                   hipMemcpyHostToDevice, c->stream);
@@ -970,7 +987,7 @@ int pibm_init(pibm_ctx **out, const pibm_params *p, const pibm_particle *pt, int
     if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
     if (e != hipSuccess) { delete c; return PIBM_EDEVICE; }
     // zeroed small state: tile starts (no particles => empty lists), history counts, error word
-    const int zero_regions[] = {R_TSTART, R_TCOUNT, R_CCOUNT, R_CITEMS, R_CNTR, R_HN0, R_HN1, R_ERR, R_REACT};
+    const int zero_regions[] = {R_TSTART, R_TCOUNT, R_TSTART1, R_TCOUNT1, R_CCOUNT, R_CITEMS, R_CNTR, R_HN0, R_HN1, R_ERR, R_REACT};
     for (int r : zero_regions) {
         const size_t bytes = c->P.off[r + 1] - c->P.off[r];
         hipLaunchKernelGGL(k_fill_int, dim3(std::max<size_t>(1, std::min<size_t>(1024, (bytes / 4 + 255) / 256))), dim3(256), 0,
@@ -1197,7 +1214,7 @@ int pibm_load(pibm_ctx *c, const void *buf, size_t n)
         if (e != hipSuccess) return hip_ok(c, e);
         o += b;
     }
-    c->cur = h.cur; c->pcur = h.pcur; c->hcur = h.hcur; c->step = h.step; c->cells_ok = 0;
+    c->cur = h.cur; c->pcur = h.pcur; c->hcur = h.hcur; c->step = h.step; c->cells_ok = 0; c->tiles_next = 0;
     return hip_ok(c, hipStreamSynchronize(c->stream));
 }
 
