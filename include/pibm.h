@@ -112,9 +112,9 @@ typedef struct pibm_params {
                                 wall of the last blocked axis sets a diagonal's Dirichlet value) */
     int streams;             /* 0: automatic (two streams on lattices of at least 2^22 nodes, one
                                 below, where the cross-stream waits cost more than they hide);
-                                1: every launch on the caller's stream; 2: binning beside the
-                                exchange and the DEM beside the lattice kernel on a second stream.
-                                Results are identical for every choice. */
+                                1: every launch on the caller's stream; 2: the DEM and the next
+                                step's cell and tile lists beside the lattice kernel on a second
+                                stream.  Results are identical for every choice. */
 } pibm_params;
 
 enum { PIBM_FIXED = 1, PIBM_THERMO = 2 };
@@ -138,10 +138,11 @@ size_t pibm_workspace_bytes(const pibm_params *p, const pibm_particle *particles
  * 256-byte aligned) owned by the caller and borrowed until pibm_destroy;
  * hip_stream: the caller's hipStream_t (NULL = default stream) on which all
  * work is queued.  With two streams (pibm_params.streams) the context also
- * owns one non-blocking stream on that stream's device: within a step,
- * binning runs there beside the exchange and the DEM sub-steps beside the
- * lattice kernel, forked from and joined back into hip_stream by events, so
- * every call's work is complete once hip_stream is.  Validates tau > 1/2, sizes, particle overlap and containment; fills
+ * owns one non-blocking stream on that stream's device: within a step, the
+ * DEM sub-steps and the next step's cell and tile lists run there beside the
+ * lattice kernel (the first step's binning beside the exchange), forked from
+ * and joined back into hip_stream by events, so every call's work is
+ * complete once hip_stream is.  Validates tau > 1/2, sizes, particle overlap and containment; fills
  * f = w rho0, g = w T_init; uploads particles.  Returns after the uploads
  * completed; PIBM_EDEVICE if the stream or events cannot be created. */
 int pibm_init(pibm_ctx **out, const pibm_params *p, const pibm_particle *particles, int n_particles,
