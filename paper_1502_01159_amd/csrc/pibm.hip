@@ -657,6 +657,24 @@ int launch_dem(pibm_ctx *c, hipStream_t s)
     a.cur = (const DevParticle *)c->r(c->pcur ? R_PART1 : R_PART0);
     hipLaunchKernelGGL(k_neighbours, dim3((c->P.np + NBR_THREADS / 64 - 1) / (NBR_THREADS / 64)), dim3(NBR_THREADS), 0,
                        s, a);
+    if (c->P.np <= DEM_ONE_WG) {   // few particles: every sub-step in one launch
+        DemOneWg f{};
+        f.a = a;
+        f.part[0] = (DevParticle *)c->r(c->pcur ? R_PART1 : R_PART0);
+        f.part[1] = (DevParticle *)c->r(c->pcur ? R_PART0 : R_PART1);
+        f.hid[0] = (int *)c->r(c->hcur ? R_HID1 : R_HID0);
+        f.hid[1] = (int *)c->r(c->hcur ? R_HID0 : R_HID1);
+        f.hxi[0] = (double *)c->r(c->hcur ? R_HXI1 : R_HXI0);
+        f.hxi[1] = (double *)c->r(c->hcur ? R_HXI0 : R_HXI1);
+        f.hn[0] = (int *)c->r(c->hcur ? R_HN1 : R_HN0);
+        f.hn[1] = (int *)c->r(c->hcur ? R_HN0 : R_HN1);
+        f.n_sub = c->p.n_sub;
+        const int threads = (c->P.np + 63) / 64 * 64;
+        hipLaunchKernelGGL(k_dem_one_wg, dim3(1), dim3(threads), 0, s, f);
+        if (c->p.n_sub & 1) { c->pcur ^= 1; c->hcur ^= 1; }
+        c->cells_ok = 0;
+        return hip_ok(c, hipGetLastError());
+    }
     for (int k = 0; k < c->p.n_sub; ++k) {
         a.cur = (const DevParticle *)c->r(c->pcur ? R_PART1 : R_PART0);
         a.nxt = (DevParticle *)c->r(c->pcur ? R_PART0 : R_PART1);

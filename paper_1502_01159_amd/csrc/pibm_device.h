@@ -1952,6 +1952,36 @@ __global__ void k_dem(DemArgs a)
     if (i < a.np) dem_particle(a, i);
 }
 
+// Every sub-step in one workgroup, one thread per particle (np <=
+// DEM_ONE_WG): the particle and contact-history buffers alternate as between
+// k_dem launches and a barrier separates the sub-steps.  Each particle reads
+// only the previous sub-step's buffers and writes its own slots, so the
+// results are those of k_dem; for a few hundred particles one launch costs
+// less than one per sub-step.
+struct DemOneWg {
+    DemArgs a;                     // cur / nxt and the history pointers are set per sub-step
+    DevParticle *part[2];          // part[0] holds the state at the first sub-step
+    int *hid[2], *hn[2];           // hid[0], hn[0], hxi[0]: the history at the first sub-step
+    double *hxi[2];
+    int n_sub;
+};
+constexpr int DEM_ONE_WG = 512;
+
+__global__ __launch_bounds__(DEM_ONE_WG) void k_dem_one_wg(DemOneWg f)
+{
+    for (int s = 0; s < f.n_sub; ++s) {
+        DemArgs a = f.a;
+        const int c = s & 1;
+        a.cur = f.part[c];
+        a.nxt = f.part[c ^ 1];
+        a.hid_in = f.hid[c]; a.hxi_in = f.hxi[c]; a.hn_in = f.hn[c];
+        a.hid_out = f.hid[c ^ 1]; a.hxi_out = f.hxi[c ^ 1]; a.hn_out = f.hn[c ^ 1];
+        a.last = s == f.n_sub - 1;
+        if ((int)threadIdx.x < a.np) dem_particle(a, threadIdx.x);
+        __syncthreads();
+    }
+}
+
 
 // Initial state: f = w rho0 and g = w T_init, i.e. deviations 0 and
 // w (T_init - T_ref).
