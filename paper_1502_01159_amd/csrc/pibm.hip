@@ -472,6 +472,10 @@ template <class T> LbmArgs<T> lbm_args(const pibm_ctx *c)
     return a;
 }
 
+// Cell lists of at most this many particles and cells are built by one
+// workgroup in one launch instead of four launches.
+constexpr int ONE_WG_PARTICLES = 256, ONE_WG_LISTS = 16384;
+
 int hip_ok(pibm_ctx *c, hipError_t e)
 {
     if (e == hipSuccess) return PIBM_OK;
@@ -638,6 +642,11 @@ int build_cells(pibm_ctx *c, hipStream_t s)
     const int gb = (c->P.np + 127) / 128;
     a.cur = (const DevParticle *)c->r(c->pcur ? R_PART1 : R_PART0);
     int *cntr = (int *)c->r(R_CNTR) + 1;
+    if (c->P.np <= ONE_WG_PARTICLES && c->P.ncells <= ONE_WG_LISTS) {   // few particles: one launch
+        hipLaunchKernelGGL(k_cells_one_wg, dim3(1), dim3(ONE_WG), 0, s, a, (int)c->P.ncells, cntr);
+        c->cells_ok = 1;
+        return hip_ok(c, hipGetLastError());
+    }
     hipLaunchKernelGGL(k_zero2, dim3(std::min(1024, (c->P.ncells + 256) / 256)), dim3(256), 0, s,
                        a.cell_count, (long long)c->P.ncells, cntr, 1LL);
     hipLaunchKernelGGL((k_cells<false>), dim3(gb), dim3(128), 0, s, a);

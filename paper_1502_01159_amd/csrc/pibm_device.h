@@ -1533,10 +1533,9 @@ __device__ __forceinline__ int axis_tile(const AxisRun &r, int i) { return i < r
 // particle's patch, so the lattice kernel scans only the points near a tile.
 constexpr int BIN_THREADS = 256;
 template <bool FILL>
-__global__ __launch_bounds__(BIN_THREADS) void k_bin(BinArgs a)
+__device__ __forceinline__ void bin_particle(const BinArgs &a, int p, int lane)
 {
-    const int p = blockIdx.x * (BIN_THREADS / 64) + (threadIdx.x >> 6), lane = threadIdx.x & 63;
-    if (p >= a.np || halted(a.err)) return;
+    if (halted(a.err)) return;                     // uniform over the wave, as every early return here
     const DevParticle P = a.part[p];
     // a non-finite or runaway centre would give meaningless loop bounds
     bool finite = true;
@@ -1601,6 +1600,13 @@ __global__ __launch_bounds__(BIN_THREADS) void k_bin(BinArgs a)
             }
         }
     }
+}
+
+template <bool FILL>
+__global__ __launch_bounds__(BIN_THREADS) void k_bin(BinArgs a)
+{
+    const int p = blockIdx.x * (BIN_THREADS / 64) + (threadIdx.x >> 6), lane = threadIdx.x & 63;
+    if (p < a.np) bin_particle<FILL>(a, p, lane);
 }
 
 __global__ void k_fill_int(int *p, long long n, int v)
@@ -1670,10 +1676,9 @@ struct DemArgs {
 };
 
 template <bool FILL>
-__global__ void k_cells(DemArgs a)
+__device__ __forceinline__ void cell_particle(const DemArgs &a, int p)
 {
-    const int p = blockIdx.x * blockDim.x + threadIdx.x;
-    if (p >= a.np || halted(a.err)) return;
+    if (halted(a.err)) return;
     const DevParticle P = a.cur[p];
     const int cx = cell_coord(P.x[0], a.nx, a.per[0], a.ncx, a.cwx);
     const int cy = cell_coord(P.x[1], a.ny, a.per[1], a.ncy, a.cwy);
@@ -1685,6 +1690,54 @@ __global__ void k_cells(DemArgs a)
     } else {
         atomicAdd(&a.cell_count[c], 1);
     }
+}
+
+template <bool FILL>
+__global__ void k_cells(DemArgs a)
+{
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p < a.np) cell_particle<FILL>(a, p);
+}
+
+// Few particles: the four phases of the cell list (zero, count, ranges,
+// fill: k_zero2, k_cells, k_alloc, k_cells) in one workgroup, barriers
+// between the phases.  The list is the same up to the order of items within
+// a cell, which no result depends on.  Counts built by device-scope atomics
+// are read back with atomic loads.
+constexpr int ONE_WG = 1024;
+__device__ __forceinline__ void alloc_one_wg(const int *count, int *start, int *fill, int n, int *total)
+{
+    const int tid = threadIdx.x, lane = tid & 63;
+    for (int b = 0; b < n; b += ONE_WG) {
+        const int i = b + tid;
+        const int c = i < n ? __atomic_load_n(&count[i], __ATOMIC_RELAXED) : 0;
+        int incl = c;
+#pragma unroll
+        for (int d = 1; d < 64; d <<= 1) {
+            const int y = __shfl_up(incl, d);
+            if (lane >= d) incl += y;
+        }
+        int base = 0;
+        if (lane == 63) base = atomicAdd(total, incl);
+        base = __shfl(base, 63);
+        if (i < n) {
+            start[i] = base + incl - c;
+            fill[i] = 0;
+        }
+    }
+}
+
+__global__ __launch_bounds__(ONE_WG) void k_cells_one_wg(DemArgs a, int ncells, int *total)
+{
+    const int tid = threadIdx.x;
+    for (int i = tid; i < ncells; i += ONE_WG) a.cell_count[i] = 0;
+    if (tid == 0) *total = 0;
+    __syncthreads();
+    for (int p = tid; p < a.np; p += ONE_WG) cell_particle<false>(a, p);
+    __syncthreads();
+    alloc_one_wg(a.cell_count, a.cell_start, a.cell_fill, ncells, total);
+    __syncthreads();
+    for (int p = tid; p < a.np; p += ONE_WG) cell_particle<true>(a, p);
 }
 
 __device__ __forceinline__ void min_image(const DemArgs &a, const double *xi, const double *xj, double *d)
