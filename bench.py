@@ -109,7 +109,7 @@ def time_gpu(cfg, P, storage, steps, warmup, phase_steps=0):
 
 def copy_probe(nbytes=1 << 30, reps=10):
     """A plain device copy of known size (one elementwise kernel: every byte
-    read once and written once).  Gives the box's achievable copy bandwidth
+    read once and written once).  Gives the device's achievable copy bandwidth
     and, under rocprofv3 --pmc, the scale of the FETCH_SIZE / WRITE_SIZE
     counters."""
     import torch
