@@ -273,6 +273,25 @@ def test_two_streams_match_one_stream(gpu, case, storage):
         assert np.array_equal(a, b)
 
 
+def test_neighbour_capacity_reports_enomem(gpu):
+    """More neighbour candidates than a particle's list holds (32): the
+    device's own bounds check stops the list at capacity and reports
+    PIBM_ENOMEM; later steps are refused.  A 5^3 block of point particles at
+    pitch 0.6 with skin 1 gives the central one 80 candidates."""
+    cfg = dict(dim=3, nx=12, ny=12, nz=12, periodic=[1, 1, 1], T_wall=[0.0] * 6, T_init=0.0, T_ref=0.0,
+               Ra=0.0, nu=0.1, Pr=0.7, Gr=0.0, Lc=8.0, gravity=0.0, kappa_T=1.0, marker_mode=2,
+               marker_spacing=1.0, E_star=10.0, poisson=0.33, mu_fric=0.3, n_sub=1, beta_p=0.0, c_r=1.0,
+               skin=1.0)
+    P = np.array([[4.0 + 0.6 * i, 4.0 + 0.6 * j, 4.0 + 0.6 * k, 0, 0, 0, 0, 0, 0, 0.25, 1.0, 0.0, W.FIXED]
+                  for i in range(5) for j in range(5) for k in range(5)])
+    s = gpu.Simulation(cfg, P, storage="f32")
+    s.step(1)
+    assert s.sync() == gpu.ENOMEM
+    with pytest.raises(gpu.PibmError):
+        s.step(1)
+    s.close()
+
+
 def test_profile_phases(gpu):
     """Phase profiling times only the phases in the mask; the full mask times
     all four; bits beyond the phases are refused."""
