@@ -42,55 +42,68 @@ class OrcParams(ctypes.Structure):
     ]
 
 
-def build(force: bool = False) -> str:
-    """Compile the oracle with gcc (portable x86-64 flags, IEEE arithmetic)."""
+def compile_library(src: str, out: str) -> str:
+    """gcc the oracle source ``src`` into the shared library ``out`` (portable
+    x86-64 flags, IEEE arithmetic: no fast-math, no FMA contraction)."""
     import subprocess
 
+    tmp = out + ".tmp"
+    subprocess.check_call(["gcc", "-O2", "-fopenmp", "-fno-fast-math", "-ffp-contract=off",
+                           "-shared", "-fPIC", "-o", tmp, src, "-lm"])
+    os.replace(tmp, out)
+    return out
+
+
+def build(force: bool = False) -> str:
+    """Compile the oracle next to its source if it is missing or stale."""
     if force or not os.path.exists(LIB_PATH) or os.path.getmtime(LIB_PATH) < os.path.getmtime(SRC_PATH):
-        tmp = LIB_PATH + ".tmp"
-        subprocess.check_call(["gcc", "-O2", "-fopenmp", "-fno-fast-math", "-ffp-contract=off",
-                               "-shared", "-fPIC", "-o", tmp, SRC_PATH, "-lm"])
-        os.replace(tmp, LIB_PATH)
+        compile_library(SRC_PATH, LIB_PATH)
     return LIB_PATH
 
 
 _lib = None
 
 
+def load(path: str):
+    """Open an oracle library at ``path`` and declare its C signatures."""
+    L = ctypes.CDLL(path)
+    vp, dp, ip = ctypes.c_void_p, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int)
+    L.orc_create.restype = vp
+    L.orc_create.argtypes = [ctypes.POINTER(OrcParams), ctypes.c_int, dp]
+    L.orc_destroy.argtypes = [vp]
+    L.orc_step.argtypes = [vp, ctypes.c_int]
+    L.orc_dem_only.argtypes = [vp, ctypes.c_int]
+    L.orc_clear_reactions.argtypes = [vp]
+    L.orc_num_nodes.restype = ctypes.c_long
+    L.orc_num_nodes.argtypes = [vp]
+    L.orc_num_markers.argtypes = [vp, ctypes.c_int]
+    L.orc_error.argtypes = [vp]
+    L.orc_get_populations.argtypes = [vp, dp, dp]
+    L.orc_set_populations.argtypes = [vp, dp, dp]
+    L.orc_get_particles.argtypes = [vp, dp]
+    L.orc_set_particles.argtypes = [vp, dp]
+    L.orc_get_reactions.argtypes = [vp, dp]
+    L.orc_get_markers.argtypes = [vp, ctypes.c_int, dp]
+    L.orc_fields.argtypes = [vp, dp, dp, dp, dp, dp]
+    L.orc_totals.argtypes = [vp, dp]
+    L.orc_raw_moments.argtypes = [vp, dp, dp, dp]
+    L.orc_exchange.argtypes = [vp]
+    L.orc_contacts.argtypes = [vp, ctypes.c_int, ip]
+    L.orc_delta_h.restype = ctypes.c_double
+    L.orc_delta_h.argtypes = [ctypes.c_double]
+    L.orc_lagrange2.restype = ctypes.c_double
+    L.orc_lagrange2.argtypes = [ctypes.c_double, ctypes.c_int, ctypes.c_int]
+    L.orc_num_threads.restype = ctypes.c_int
+    return L
+
+
 def lib():
+    """The oracle library built next to its source."""
     global _lib
     if _lib is None:
         if not os.path.exists(LIB_PATH):
             build()
-        L = ctypes.CDLL(LIB_PATH)
-        vp, dp, ip = ctypes.c_void_p, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int)
-        L.orc_create.restype = vp
-        L.orc_create.argtypes = [ctypes.POINTER(OrcParams), ctypes.c_int, dp]
-        L.orc_destroy.argtypes = [vp]
-        L.orc_step.argtypes = [vp, ctypes.c_int]
-        L.orc_dem_only.argtypes = [vp, ctypes.c_int]
-        L.orc_clear_reactions.argtypes = [vp]
-        L.orc_num_nodes.restype = ctypes.c_long
-        L.orc_num_nodes.argtypes = [vp]
-        L.orc_num_markers.argtypes = [vp, ctypes.c_int]
-        L.orc_error.argtypes = [vp]
-        L.orc_get_populations.argtypes = [vp, dp, dp]
-        L.orc_set_populations.argtypes = [vp, dp, dp]
-        L.orc_get_particles.argtypes = [vp, dp]
-        L.orc_set_particles.argtypes = [vp, dp]
-        L.orc_get_reactions.argtypes = [vp, dp]
-        L.orc_get_markers.argtypes = [vp, ctypes.c_int, dp]
-        L.orc_fields.argtypes = [vp, dp, dp, dp, dp, dp]
-        L.orc_totals.argtypes = [vp, dp]
-        L.orc_raw_moments.argtypes = [vp, dp, dp, dp]
-        L.orc_exchange.argtypes = [vp]
-        L.orc_contacts.argtypes = [vp, ctypes.c_int, ip]
-        L.orc_delta_h.restype = ctypes.c_double
-        L.orc_delta_h.argtypes = [ctypes.c_double]
-        L.orc_lagrange2.restype = ctypes.c_double
-        L.orc_lagrange2.argtypes = [ctypes.c_double, ctypes.c_int, ctypes.c_int]
-        L.orc_num_threads.restype = ctypes.c_int
-        _lib = L
+        _lib = load(LIB_PATH)
     return _lib
 
 
@@ -158,13 +171,14 @@ class Oracle:
     """One FP64 simulation.  ``particles`` is an (n, 13) array:
     x[3] u[3] omega[3] R rho_r T flags (flags: 1 fixed, 2 thermosensitive)."""
 
-    def __init__(self, cfg: dict, particles=None):
+    def __init__(self, cfg: dict, particles=None, library=None):
+        self._L = library if library is not None else lib()
         self.cfg = dict(cfg)
         self.derived = derive(cfg)
         self.params = make_params(cfg)
         P = np.zeros((0, 13)) if particles is None else np.ascontiguousarray(particles, dtype=np.float64)
         self.np = P.shape[0]
-        L = lib()
+        L = self._L
         self._h = L.orc_create(ctypes.byref(self.params), self.np, _dp(P) if self.np else None)
         self.dim = self.params.dim
         self.shape = (self.params.nz, self.params.ny, self.params.nx)
@@ -175,53 +189,53 @@ class Oracle:
     def __del__(self):
         h = getattr(self, "_h", None)
         if h:
-            lib().orc_destroy(h)
+            self._L.orc_destroy(h)
             self._h = None
 
     def step(self, n: int = 1):
-        lib().orc_step(self._h, int(n))
+        self._L.orc_step(self._h, int(n))
 
     def dem_only(self, n: int = 1):
-        lib().orc_dem_only(self._h, int(n))
+        self._L.orc_dem_only(self._h, int(n))
 
     def clear_reactions(self):
-        lib().orc_clear_reactions(self._h)
+        self._L.orc_clear_reactions(self._h)
 
     @property
     def error(self) -> int:
-        return lib().orc_error(self._h)
+        return self._L.orc_error(self._h)
 
     def populations(self):
         f = np.empty((self.Q, self.N))
         g = np.empty((self.Qg, self.N))
-        lib().orc_get_populations(self._h, _dp(f), _dp(g))
+        self._L.orc_get_populations(self._h, _dp(f), _dp(g))
         return f, g
 
     def set_populations(self, f, g):
         f = np.ascontiguousarray(f, dtype=np.float64).reshape(self.Q, self.N)
         g = np.ascontiguousarray(g, dtype=np.float64).reshape(self.Qg, self.N)
-        lib().orc_set_populations(self._h, _dp(f), _dp(g))
+        self._L.orc_set_populations(self._h, _dp(f), _dp(g))
 
     def particles(self):
         out = np.empty((self.np, 16))
         if self.np:
-            lib().orc_get_particles(self._h, _dp(out))
+            self._L.orc_get_particles(self._h, _dp(out))
         return out
 
     def set_particles(self, P):
         P = np.ascontiguousarray(P, dtype=np.float64)
-        lib().orc_set_particles(self._h, _dp(P))
+        self._L.orc_set_particles(self._h, _dp(P))
 
     def reactions(self):
         out = np.empty((self.np, 8))
         if self.np:
-            lib().orc_get_reactions(self._h, _dp(out))
+            self._L.orc_get_reactions(self._h, _dp(out))
         return out
 
     def markers(self, i: int):
-        n = lib().orc_num_markers(self._h, i)
+        n = self._L.orc_num_markers(self._h, i)
         out = np.empty((n, 4))
-        lib().orc_get_markers(self._h, i, _dp(out))
+        self._L.orc_get_markers(self._h, i, _dp(out))
         return out
 
     def fields(self, forcing: bool = False):
@@ -231,7 +245,7 @@ class Oracle:
         T = np.empty(self.N)
         FB = np.empty(self.N * 3) if forcing else None
         QB = np.empty(self.N) if forcing else None
-        lib().orc_fields(self._h, _dp(rho), _dp(u), _dp(T),
+        self._L.orc_fields(self._h, _dp(rho), _dp(u), _dp(T),
                          _dp(FB) if forcing else None, _dp(QB) if forcing else None)
         out = (rho.reshape(self.shape), u.reshape(self.shape + (3,)), T.reshape(self.shape))
         if forcing:
@@ -241,22 +255,22 @@ class Oracle:
     def raw_moments(self):
         """Post-stream rho (N), j (N, 3), S (N) of the current state."""
         rho, j, S = np.empty(self.N), np.empty(3 * self.N), np.empty(self.N)
-        lib().orc_raw_moments(self._h, _dp(rho), _dp(j), _dp(S))
+        self._L.orc_raw_moments(self._h, _dp(rho), _dp(j), _dp(S))
         return rho, j.reshape(self.N, 3), S
 
     def exchange(self):
         """Evaluate the point exchange on the current state; its reactions
         become what reactions() returns."""
-        lib().orc_exchange(self._h)
+        self._L.orc_exchange(self._h)
 
     def totals(self):
         out = np.empty(5)
-        lib().orc_totals(self._h, _dp(out))
+        self._L.orc_totals(self._h, _dp(out))
         return out
 
     def contacts(self, i: int):
         buf = (ctypes.c_int * max(self.np, 1))()
-        n = lib().orc_contacts(self._h, i, buf)
+        n = self._L.orc_contacts(self._h, i, buf)
         return [buf[k] for k in range(n)]
 
 

@@ -297,8 +297,15 @@ def test_interpolation_exact_for_linear_fields(oracle_mod, dim):
     expect_F = -(Fl * A[:, None]).sum(0)
     Tl = s_lin(X[:, 0], X[:, 1], X[:, 2])
     expect_H = (2.0 * (0.8 - Tl) * A).sum()
+    # Eq. (lbm13): the torque is the moment of the same point forces about
+    # the centre, tau = -sum_l r_l x F_l A_l (2D: its z component only)
+    expect_T = -np.cross(r, Fl * A[:, None]).sum(0)
+    if dim == 2:
+        expect_T[:2] = 0.0
     got = o.reactions()[0]
     assert np.allclose(got[:3], expect_F, rtol=1e-12, atol=1e-14)
+    assert np.allclose(got[3:6], expect_T, rtol=1e-12, atol=1e-14)
+    assert np.abs(expect_T).max() > 1e-3              # the rotation and the gradients give a real moment
     assert got[6] == pytest.approx(expect_H, rel=1e-12)
 
 
@@ -343,15 +350,20 @@ def test_interpolation_exact_for_cubic_fields_order4(oracle_mod, dim):
         rl = rho_c(X[:, 0], X[:, 1], X[:, 2])
         jl = np.zeros_like(X)
         jl[:, 0] = jx_c(X[:, 0], X[:, 1], X[:, 2])
-        expect_F = -((2.0 * (rl[:, None] * Ul - jl)) * A[:, None]).sum(0)
+        FA = (2.0 * (rl[:, None] * Ul - jl)) * A[:, None]
+        expect_F = -FA.sum(0)
+        expect_T = -np.cross(r, FA).sum(0)
+        if dim == 2:
+            expect_T[:2] = 0.0
         expect_H = (2.0 * (0.8 - s_c(X[:, 0], X[:, 1], X[:, 2])) * A).sum()
         got = o.reactions()[0]
-        return got, expect_F, expect_H
+        return got, expect_F, expect_H, expect_T
 
-    got, eF, eH = run(4)
+    got, eF, eH, eT = run(4)
     assert np.allclose(got[:3], eF, rtol=1e-11, atol=1e-13)
+    assert np.allclose(got[3:6], eT, rtol=1e-11, atol=1e-13)
     assert got[6] == pytest.approx(eH, rel=1e-11)
-    got2, eF2, eH2 = run(2)
+    got2, eF2, eH2, _ = run(2)
     assert abs(got2[6] - eH2) > 1e-6 * abs(eH2)
 
 
@@ -439,6 +451,38 @@ def test_stokes_drag_periodic_array(oracle_mod):
     a2 = radius()
     assert abs(a2 - a1) < 1e-2 * a2
     assert R <= a2 <= R + 1.0
+
+
+def test_rotlet_torque_spinning_sphere(oracle_mod):
+    """The fluid torque of Eq. (lbm13) against Stokes flow: a fixed sphere
+    spinning slowly at Omega in fluid at rest feels the torque -8 pi mu a^3
+    Omega (the rotlet), anti-parallel to the spin, with no net force.  As in
+    the drag pin the diffuse interface's hydrodynamic radius a lies within
+    [R, R + 1]; the periodic images change the torque by O(phi), 1% here.
+    The spin axis is oblique to the lattice, so every torque component and
+    the moment of inertia-free part of the exchange (U_l = Omega x r_l) are
+    exercised; the reading must be steady (two readings 150 steps apart)."""
+    L, R, tau, Om = 32, 4.0, 1.0, 1e-3
+    nu = (tau - 0.5) / 3.0
+    cfg = base3d(nx=L, ny=L, nz=L, nu=nu)
+    c = (L - 1) / 2.0
+    Omv = np.array([0.3, -0.2, 1.0]) * Om
+    o = oracle_mod.Oracle(cfg, np.array([prow((c, c, c), R, flags=W.FIXED, om=Omv)]))
+
+    def radius():
+        tq = o.reactions()[0][3:6]
+        par = -tq @ Omv / (Omv @ Omv)
+        return (par / (8.0 * math.pi * nu)) ** (1.0 / 3.0), tq
+
+    o.step(450)
+    a1, _ = radius()
+    o.step(150)
+    a2, tq = radius()
+    F = o.reactions()[0][:3]
+    assert abs(a2 - a1) < 1e-3 * a2
+    assert R <= a2 <= R + 1.0
+    assert -tq @ Omv / (np.linalg.norm(tq) * np.linalg.norm(Omv)) > 1.0 - 1e-6
+    assert np.linalg.norm(F) < 1e-3 * np.linalg.norm(tq) / R
 
 
 def test_fixed_hot_body_heats_fluid_and_drag_opposes_motion(oracle_mod):
@@ -574,6 +618,112 @@ def test_contact_list_brute_force(oracle_mod):
     assert o.contacts(0) == [1, 2]       # 1 through the periodic x face
     assert o.contacts(2) == [0]
     assert o.contacts(3) == []           # touching at distance R_i + R_j exactly is no contact
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+@pytest.mark.parametrize("thermo", [False, True])
+def test_free_fall_reduced_gravity(oracle_mod, dim, thermo):
+    """Eq. (demgov): with no fluid and no contact a particle accelerates by
+    the buoyancy-reduced gravity a = -(1 - rho_f / rho_p) g along the up axis
+    (-y in 2D, -z in 3D).  A thermosensitive particle takes the density of
+    Sec. 3.4, rho_p = rho_r (1 - beta_p (T_p - T_ref)): here one hot enough to
+    be lighter than the fluid, which must rise.  Semi-implicit Euler over K
+    sub-steps of length dts gives U_K = a K dts and
+    X_K = X_0 + a dts^2 K (K + 1) / 2 exactly (up to round-off)."""
+    g, n_sub, nsteps = 2e-3, 3, 7
+    cfg = (base2d if dim == 2 else base3d)(nx=64, ny=64, nz=64, periodic=[1, 1, 1], gravity=g, n_sub=n_sub,
+                                           T_ref=0.2, beta_p=0.05)
+    rho_r, T = (1.02, 1.4) if thermo else (1.5, 0.9)
+    x0 = (31.3, 30.2, 29.7 if dim == 3 else 0.0)
+    o = oracle_mod.Oracle(cfg, np.array([prow(x0, 3.0, rho_r, T=T, flags=W.THERMO if thermo else 0)]))
+    o.clear_reactions()
+    o.dem_only(nsteps)
+    rho_p = rho_r * (1.0 - 0.05 * (T - 0.2)) if thermo else rho_r
+    a = -g * (1.0 - 1.0 / rho_p)
+    if thermo:
+        assert a > 0                                  # the hot particle is lighter than the fluid
+    up = dim - 1
+    K, dts = nsteps * n_sub, 1.0 / n_sub
+    q = o.particles()[0]
+    for c in range(3):
+        if c == up:
+            assert q[3 + c] == pytest.approx(a * K * dts, rel=1e-13)
+            assert q[c] - x0[c] == pytest.approx(a * dts * dts * K * (K + 1) / 2.0, rel=1e-12)
+        else:
+            assert q[3 + c] == 0.0 and q[c] == x0[c]
+    assert np.all(q[6:12] == 0.0)                     # no torque, no rotation
+    assert q[14] == T                                 # no heat exchange without fluid
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+def test_sliding_on_floor_conserves_contact_angular_momentum(oracle_mod, dim):
+    """Sec. 2.3 with Eq. (demgov): a body launched sliding (U0 along x, no
+    spin) on a floor, pressed on it by the reduced gravity.  Gravity and the
+    normal force have no moment about the contact line, so the friction's
+    impulse changes U and Omega in the fixed ratio I dOmega = -/+ m R dU:
+    I Omega_y + m R U_x (sphere) and I Omega_z - m R U_x (disk, per unit
+    depth) stay at m R U0 after every sub-step, with I = 2/5 m R^2 (sphere)
+    and 1/2 m R^2 (disk).  Once the slip has stopped the body rolls at
+    U0 / (1 + I / (m R^2)) = 5/7 U0 (sphere) and 2/3 U0 (disk), the
+    textbook result."""
+    R, rho_r, g, E, mu, n_sub = 4.0, 2.0, 1e-3, 200.0, 0.3, 4
+    mk = base2d if dim == 2 else base3d
+    cfg = mk(nx=200, ny=40, nz=40, periodic=[1, 0, 1] if dim == 2 else [1, 1, 0], gravity=g, E_star=E,
+             mu_fric=mu, n_sub=n_sub)
+    V = math.pi * R * R if dim == 2 else 4.0 / 3.0 * math.pi * R ** 3
+    m = rho_r * V
+    I = (0.5 if dim == 2 else 0.4) * m * R * R
+    # rest overlap where the Hertz force carries the reduced weight
+    W_ = m * g * (1.0 - 1.0 / rho_r)
+    delta = (W_ / (4.0 / 3.0 * E * math.sqrt(R))) ** (2.0 / 3.0)
+    U0 = 0.02
+    c = [100.0, 20.0, 20.0]
+    c[dim - 1] = R - 0.5 - delta
+    if dim == 2:
+        c[2] = 0.0
+    o = oracle_mod.Oracle(cfg, np.array([prow(c, R, rho_r, u=(U0, 0.0, 0.0))]))
+    o.clear_reactions()
+    L0 = m * R * U0
+    om_axis, sgn = (2, -1.0) if dim == 2 else (1, 1.0)
+    hist = []
+    for _ in range(400):
+        o.dem_only(1)
+        q = o.particles()[0]
+        assert I * sgn * q[6 + om_axis] + m * R * q[3] == pytest.approx(L0, rel=1e-12)
+        hist.append((q[3], sgn * q[6 + om_axis] * R))
+    hist = np.array(hist[150:])                       # the slip stopped after ~60 steps
+    assert hist[:, 0].max() < 0.8 * U0                # friction acted
+    # once stuck, the tangential spring makes U oscillate about the rolling
+    # speed: compare the average over many periods
+    roll = 1.0 / (1.0 + I / (m * R * R))
+    assert hist[:, 0].mean() == pytest.approx(roll * U0, rel=2e-3)
+    assert hist[:, 1].mean() == pytest.approx(roll * U0, rel=2e-3)   # rolling: contact point at rest
+
+
+def test_pair_contact_torque_lever_arms(oracle_mod):
+    """Sec. 2.3: in a contact between spheres of different radius and density
+    each body receives the tangential force at its own surface point, so its
+    torque is R_i n x F_t and R_j n x F_t with the same n x F_t.  Starting
+    without spin and without fluid, 2/5 m_i R_i Omega_i = 2/5 m_j R_j Omega_j
+    (I / R times Omega) after every sub-step of a glancing collision, and the
+    linear momenta stay opposite."""
+    cfg = _dem_cfg(3, E=60.0, mu=0.3, n_sub=4, n=60)
+    Ri, Rj, ri, rj = 4.0, 2.5, 1.5, 3.0
+    P = np.array([prow((26.0, 30.0, 30.0), Ri, ri, u=(0.02, 0.0, 0.004)),
+                  prow((32.2, 31.5, 30.8), Rj, rj, u=(-0.01, -0.002, 0.0))])
+    o = oracle_mod.Oracle(cfg, P)
+    o.clear_reactions()
+    mi, mj = ri * 4.0 / 3.0 * math.pi * Ri ** 3, rj * 4.0 / 3.0 * math.pi * Rj ** 3
+    p0 = mi * P[0, 3:6] + mj * P[1, 3:6]
+    spun = False
+    for _ in range(200):
+        o.dem_only(1)
+        q = o.particles()
+        Li, Lj = 0.4 * mi * Ri * q[0, 6:9], 0.4 * mj * Rj * q[1, 6:9]
+        assert np.allclose(Li, Lj, rtol=1e-11, atol=1e-16)
+        assert np.allclose(mi * q[0, 3:6] + mj * q[1, 3:6], p0, rtol=1e-12, atol=1e-16)
+        spun = spun or np.abs(Li).max() > 1e-3
+    assert spun                                       # the contact did transmit a tangential force
 
 
 # --------------------------------------------------------------------------- #
