@@ -550,7 +550,7 @@ int launch_closure(pibm_ctx *c)
     if ((st = pibm_mlp_forward_on(c->closure, c->r(R_XBF), (float *)c->r(R_YMLP), c->P.np, c->stream))) return st;
     hipLaunchKernelGGL((k_closure<DIM, T>), dim3((c->P.np + 127) / 128), dim3(128), 0, c->stream,
                        (const DevParticle *)c->r(c->pcur ? R_PART1 : R_PART0), c->P.np, (const float *)c->r(R_YMLP),
-                       (const float *)c->r(R_NORM), (const float *)c->r(R_AUX), c->d.nu, c->d.alpha,
+                       (const float *)c->r(R_NORM), (const float *)c->r(R_AUX), c->d.nu, c->d.alpha, c->p.kappa_T,
                        (MarkerRec<T> *)c->r(R_MK), (DevReact *)c->r(R_REACT), (const int *)c->r(R_ERR));
     return hip_ok(c, hipGetLastError());
 }

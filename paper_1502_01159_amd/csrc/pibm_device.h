@@ -1444,7 +1444,7 @@ __global__ void k_targets(const DevParticle *part, int np, const DevReact *react
 // no lever arm).
 template <int DIM, class T>
 __global__ void k_closure(const DevParticle *part, int np, const float *y, const float *norm, const float *aux,
-                          double nu, double alpha, MarkerRec<T> *mk, DevReact *react, const int *err)
+                          double nu, double alpha, double kappa, MarkerRec<T> *mk, DevReact *react, const int *err)
 {
     const int p = blockIdx.x * blockDim.x + threadIdx.x;
     if (p >= np || halted(err)) return;
@@ -1474,7 +1474,8 @@ __global__ void k_closure(const DevParticle *part, int np, const float *y, const
 #pragma unroll
     for (int c = 0; c < 3; ++c) { R.F[c] = F[c]; R.tq[c] = 0.0; }
     R.H = H;
-    R.dTA = 0.5 * H;
+    // the exchange's sum (T_p - T_l) A that would give this heat: H = 2 kappa_T sum (T_p - T_l) A
+    R.dTA = kappa != 0.0 ? H / (2.0 * kappa) : 0.0;
     react[p] = R;
 }
 
