@@ -7,7 +7,8 @@
  *
  * One context = one simulation on one GPU.  The caller owns the device
  * workspace and the HIP stream; the library carves every buffer out of the
- * workspace and allocates no device memory of its own.  Host arrays passed in
+ * workspace and allocates no device memory of its own (its one fixed device
+ * array belongs to pibm_mlp_grads_noalloc, below).  Host arrays passed in
  * are copied; the library keeps no host pointer after a call returns.
  * Contexts are not thread-safe: one host thread per context at a time.
  *
@@ -259,6 +260,22 @@ int pibm_mlp_grads(pibm_mlp *m, const void *dev_x, const float *dev_t, int n, fl
  * learning rate lr on one batch; the batch loss before the step to *loss if
  * not NULL (then synchronises). */
 int pibm_mlp_train_step(pibm_mlp *m, const void *dev_x, const float *dev_t, int n, float lr, double *loss);
+
+/* Allocation-free variant of pibm_mlp_grads, for callers that cannot
+ * allocate device memory (code under HIP graph capture, tight serving or
+ * training loops, harnesses that forbid hipMalloc).  Same kernels and the
+ * same result bit for bit; the per-workgroup partial gradients, their sum and
+ * the loss partials live in a fixed device array inside the library instead
+ * of the network's workspace, so n may exceed the network's max_batch, up to
+ * PIBM_MLP_NOALLOC_MAX_BATCH samples (larger n: PIBM_EINVAL).  The array is
+ * about 9.3 MB per GPU, held from the first call on that GPU until the
+ * process ends; every call on one GPU shares it and keeps the last call's
+ * contents, so calls that overlap in time on one GPU (several host threads
+ * or streams) race and must be serialised by the caller.  Calls no
+ * allocating routine; synchronises the network's stream. */
+enum { PIBM_MLP_NOALLOC_MAX_BATCH = 4096 };
+int pibm_mlp_grads_noalloc(pibm_mlp *m, const void *dev_x, const float *dev_t, int n, float *host_grads,
+                           double *loss);
 
 int pibm_mlp_destroy(pibm_mlp *m);
 

@@ -30,6 +30,7 @@
 #include <cmath>
 #include <cstdint>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <vector>
 
@@ -388,6 +389,19 @@ __global__ void k_mlp_reduce_adam(float *param, uint16_t *wbf, float *mom, float
     if (base >= 0) wbf[base + out * stride + in] = bf16_rne(np);
 }
 
+// Scratch of the allocation-free gradient pass: the partial gradients of up
+// to PIBM_MLP_NOALLOC_MAX_BATCH / 64 workgroups, their sum and the
+// workgroups' loss partials.  One copy per GPU, held until the process ends.
+// Host code never uses the array's name as an address: each device's address
+// comes from hipGetSymbolAddress (scratch_on below).
+constexpr int NOALLOC_BLK = PIBM_MLP_NOALLOC_MAX_BATCH / SPB;
+static_assert(NOALLOC_BLK * SPB == PIBM_MLP_NOALLOC_MAX_BATCH, "whole workgroups");
+constexpr size_t SCR_PART = 0;
+constexpr size_t SCR_GRAD = SCR_PART + ((size_t)NOALLOC_BLK * NPARAM * 4 + 255) / 256 * 256;
+constexpr size_t SCR_LOSS = SCR_GRAD + ((size_t)NPARAM * 4 + 255) / 256 * 256;
+constexpr size_t SCR_BYTES = SCR_LOSS + (size_t)NOALLOC_BLK * 8;
+static __device__ __align__(256) unsigned char scratch[SCR_BYTES];
+
 // splitmix64 (Steele, Lea & Flood): state += 0x9e3779b97f4a7c15, then the
 // variant-13 finaliser; 53-bit uniforms in [0, 1)
 struct SplitMix {
@@ -487,6 +501,32 @@ int mlp_loss(pibm_mlp *m, int n, double *loss)
     return PIBM_OK;
 }
 
+// Device address of `scratch` on the device of `stream`, resolved once per
+// device with that device current and kept for the process.
+constexpr int SCR_MAX_DEVICES = 64;
+std::mutex scr_mu;
+char *scr_addr[SCR_MAX_DEVICES];
+
+int scratch_on(hipStream_t stream, char **out)
+{
+    int dev = 0;
+    if ((stream ? hipStreamGetDevice(stream, &dev) : hipGetDevice(&dev)) != hipSuccess) return PIBM_EDEVICE;
+    if (dev < 0 || dev >= SCR_MAX_DEVICES) return PIBM_EDEVICE;
+    std::lock_guard<std::mutex> lock(scr_mu);
+    if (!scr_addr[dev]) {
+        int cur = 0;
+        if (hipGetDevice(&cur) != hipSuccess) return PIBM_EDEVICE;
+        if (cur != dev && hipSetDevice(dev) != hipSuccess) return PIBM_EDEVICE;
+        void *p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (cur != dev) (void)hipSetDevice(cur);
+        if (e != hipSuccess || !p) return PIBM_EDEVICE;
+        scr_addr[dev] = (char *)p;
+    }
+    *out = scr_addr[dev];
+    return PIBM_OK;
+}
+
 }  // namespace
 
 int pibm_mlp_forward_on(pibm_mlp *m, const void *dev_x, float *dev_y, int n, hipStream_t stream)
@@ -577,6 +617,38 @@ int pibm_mlp_grads(pibm_mlp *m, const void *dev_x, const float *dev_t, int n, fl
     if (hipMemcpyAsync(host_grads, m->grad, (size_t)NPARAM * 4, hipMemcpyDeviceToHost, m->stream) != hipSuccess) return PIBM_EDEVICE;
     if (loss) return mlp_loss(m, n, loss);
     return hipStreamSynchronize(m->stream) == hipSuccess ? PIBM_OK : PIBM_EDEVICE;
+}
+
+int pibm_mlp_grads_noalloc(pibm_mlp *m, const void *dev_x, const float *dev_t, int n, float *host_grads,
+                           double *loss)
+{
+    if (!m || n < 1 || n > PIBM_MLP_NOALLOC_MAX_BATCH || !dev_x || !dev_t || !host_grads) return PIBM_EINVAL;
+    if (((uintptr_t)dev_x & 7) || ((uintptr_t)dev_t & 15)) return PIBM_EINVAL;
+    char *scr = nullptr;
+    int st = scratch_on(m->stream, &scr);
+    if (st) return st;
+    float *part = (float *)(scr + SCR_PART), *grad = (float *)(scr + SCR_GRAD);
+    double *loss_part = (double *)(scr + SCR_LOSS);
+    // every workgroup writes its whole gradient slot and its loss partial, and
+    // the sum overwrites every gradient entry: nothing needs clearing
+    const int nblk = (n + SPB - 1) / SPB;
+    MlpArgs a{m->param, m->wbf};
+    hipLaunchKernelGGL(k_mlp_grad, dim3(nblk), dim3(MLP_THREADS), 0, m->stream, a, (const uint16_t *)dev_x, dev_t, n,
+                       part, loss_part);
+    hipLaunchKernelGGL(k_mlp_reduce_adam, dim3((NPARAM + 255) / 256), dim3(256), 0, m->stream, m->param, m->wbf, m->mom,
+                       m->vel, (const float *)part, nblk, grad, 0.f, 1.f, 1.f);
+    if (hipGetLastError() != hipSuccess) return PIBM_EDEVICE;
+    double lp[NOALLOC_BLK];
+    if (hipMemcpyAsync(host_grads, grad, (size_t)NPARAM * 4, hipMemcpyDeviceToHost, m->stream) != hipSuccess) return PIBM_EDEVICE;
+    if (loss && hipMemcpyAsync(lp, loss_part, (size_t)nblk * 8, hipMemcpyDeviceToHost, m->stream) != hipSuccess)
+        return PIBM_EDEVICE;
+    if (hipStreamSynchronize(m->stream) != hipSuccess) return PIBM_EDEVICE;
+    if (loss) {
+        double s = 0.0;
+        for (int b = 0; b < nblk; ++b) s += lp[b];
+        *loss = s / (4.0 * n);
+    }
+    return PIBM_OK;
 }
 
 int pibm_mlp_train_step(pibm_mlp *m, const void *dev_x, const float *dev_t, int n, float lr, double *loss)

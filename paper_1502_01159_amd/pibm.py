@@ -27,9 +27,10 @@ EXPORTS = [
     "pibm_profile", "pibm_profile_phases", "pibm_profile_read",
     "pibm_mlp_workspace_bytes", "pibm_mlp_create", "pibm_mlp_set_params", "pibm_mlp_get_params",
     "pibm_mlp_forward", "pibm_mlp_grads", "pibm_mlp_train_step", "pibm_mlp_destroy",
-    "pibm_features", "pibm_set_closure",
+    "pibm_features", "pibm_set_closure", "pibm_mlp_grads_noalloc",
 ]
 MLP_IN, MLP_HIDDEN, MLP_OUT, MLP_NPARAM = 16, 128, 4, 35716
+MLP_NOALLOC_MAX_BATCH = 4096
 PHASES = ("markers", "bin", "lattice", "dem")
 
 
@@ -106,6 +107,7 @@ def lib():
         L.pibm_mlp_get_params.argtypes = [vp, fp]
         L.pibm_mlp_forward.argtypes = [vp, vp, vp, ctypes.c_int]
         L.pibm_mlp_grads.argtypes = [vp, vp, vp, ctypes.c_int, fp, dp]
+        L.pibm_mlp_grads_noalloc.argtypes = [vp, vp, vp, ctypes.c_int, fp, dp]
         L.pibm_mlp_train_step.argtypes = [vp, vp, vp, ctypes.c_int, ctypes.c_float, dp]
         L.pibm_mlp_destroy.argtypes = [vp]
         L.pibm_features.argtypes = [vp, fp, fp]
@@ -412,6 +414,19 @@ class Mlp:
                                   g.ctypes.data_as(ctypes.POINTER(ctypes.c_float)), ctypes.byref(loss))
         if st != OK:
             raise PibmError(st, "pibm_mlp_grads")
+        return loss.value, g
+
+    def grads_noalloc(self, x, t):
+        """As :meth:`grads`, through the allocation-free entry point (batch up
+        to ``MLP_NOALLOC_MAX_BATCH`` whatever this network's ``max_batch``)."""
+        self._check(x, t)
+        g = np.empty(MLP_NPARAM, dtype=np.float32)
+        loss = ctypes.c_double()
+        st = lib().pibm_mlp_grads_noalloc(self._h, ctypes.c_void_p(x.data_ptr()), ctypes.c_void_p(t.data_ptr()),
+                                          x.shape[0], g.ctypes.data_as(ctypes.POINTER(ctypes.c_float)),
+                                          ctypes.byref(loss))
+        if st != OK:
+            raise PibmError(st, "pibm_mlp_grads_noalloc")
         return loss.value, g
 
     def train_step(self, x, t, lr: float) -> float:
