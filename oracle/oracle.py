@@ -88,12 +88,14 @@ def load(path: str):
     L.orc_totals.argtypes = [vp, dp]
     L.orc_raw_moments.argtypes = [vp, dp, dp, dp]
     L.orc_exchange.argtypes = [vp]
+    L.orc_step_prescribed.argtypes = [vp, dp]
     L.orc_contacts.argtypes = [vp, ctypes.c_int, ip]
     L.orc_delta_h.restype = ctypes.c_double
     L.orc_delta_h.argtypes = [ctypes.c_double]
     L.orc_lagrange2.restype = ctypes.c_double
     L.orc_lagrange2.argtypes = [ctypes.c_double, ctypes.c_int, ctypes.c_int]
     L.orc_num_threads.restype = ctypes.c_int
+    L.orc_set_threads.argtypes = [ctypes.c_int]
     return L
 
 
@@ -258,6 +260,13 @@ class Oracle:
         self._L.orc_raw_moments(self._h, _dp(rho), _dp(j), _dp(S))
         return rho, j.reshape(self.N, 3), S
 
+    def step_prescribed(self, FH):
+        """One one-point step with prescribed reactions FH (n, 4): the force
+        on each particle and the heat it gives the fluid, in place of the
+        Lagrangian-point exchange."""
+        FH = np.ascontiguousarray(FH, dtype=np.float64).reshape(self.np, 4)
+        self._L.orc_step_prescribed(self._h, _dp(FH))
+
     def exchange(self):
         """Evaluate the point exchange on the current state; its reactions
         become what reactions() returns."""
@@ -280,3 +289,8 @@ def delta_h(a: float) -> float:
 
 def num_threads() -> int:
     return lib().orc_num_threads()
+
+
+def set_threads(n: int) -> None:
+    """Threads of the oracle's OpenMP loops from now on."""
+    lib().orc_set_threads(int(n))

@@ -467,6 +467,31 @@ static void moments(orc_state *s)
     }
 }
 
+/* Eqs. (lbm10)-(lbm12): spread a point's force F_l A_l and heat Q_l A_l to
+ * every node within |a| < 2 of X on each axis (the nodes floor(X) - 1 ..
+ * floor(X) + 2); nodes beyond a wall are dropped, periodic axes wrap. */
+static void spread_point(orc_state *s, const double X[3], const double FA[3], double QA)
+{
+    const int dim = s->p.dim;
+    int b[3];
+    for (int d = 0; d < 3; d++) b[d] = (int)floor(X[d]);
+    int nf = dim == 2 ? 16 : 64;
+    for (int c = 0; c < nf; c++) {
+        int o[3] = {c & 3, (c >> 2) & 3, (c >> 4) & 3};
+        double W = 1.0; int idx[3] = {0, 0, 0}, out = 0;
+        for (int d = 0; d < dim; d++) {
+            int gc = b[d] - 1 + o[d];
+            W *= orc_delta_h((double)gc - X[d]);
+            idx[d] = map_coord(s, d, gc);
+            if (idx[d] < 0) out = 1;
+        }
+        if (out) continue;
+        long n = node_index(s, idx[0], idx[1], idx[2]);
+        for (int d = 0; d < 3; d++) s->FB[3*n + d] += FA[d] * W;
+        s->QB[n] += QA * W;
+    }
+}
+
 /* 3.-6. Interpolation, exchange, reactions and spreading, one particle and
  * one Lagrangian point at a time. */
 static void pibm(orc_state *s, int record_reactions)
@@ -552,23 +577,7 @@ static void pibm(orc_state *s, int record_reactions)
             Ts[2] -= r[0]*FA[1] - r[1]*FA[0];
             Hs += QA;
             dTs += (q->T - Tl) * A;
-            /* Eqs. (lbm10)-(lbm12): spread to every node within |a| < 2 on
-             * each axis; nodes beyond a wall are dropped, periodic axes wrap. */
-            int nf = dim == 2 ? 16 : 64;
-            for (int c = 0; c < nf; c++) {
-                int o[3] = {c & 3, (c >> 2) & 3, (c >> 4) & 3};
-                double W = 1.0; int idx[3] = {0, 0, 0}, out = 0;
-                for (int d = 0; d < dim; d++) {
-                    int gc = b[d] - 1 + o[d];
-                    W *= orc_delta_h((double)gc - X[d]);
-                    idx[d] = map_coord(s, d, gc);
-                    if (idx[d] < 0) out = 1;
-                }
-                if (out) continue;
-                long n = node_index(s, idx[0], idx[1], idx[2]);
-                for (int d = 0; d < 3; d++) s->FB[3*n + d] += FA[d] * W;
-                s->QB[n] += QA * W;
-            }
+            spread_point(s, X, FA, QA);
         }
         if (record_reactions) {
             for (int d = 0; d < 3; d++) { q->F[d] = Fs[d]; q->tq[d] = Ts[d]; }
@@ -693,7 +702,14 @@ static int contacts_of(const orc_state *s, int i, int *list)
 static void dem_substep(orc_state *s, double (*Fc)[3], double (*Tc)[3], orc_contact (*hist)[ORC_MAX_CONTACTS], int *nh)
 {
     const int dim = s->p.dim;
+    int overflow = 0;
+    /* Each particle's contacts are found and evaluated independently: the
+     * iteration for i reads the shared state and writes only slot i, so the
+     * particles are shared among threads without changing any result. */
+#pragma omp parallel reduction(|:overflow)
+    {
     int *list = malloc(sizeof(int) * (s->np > 0 ? s->np : 1));
+#pragma omp for schedule(dynamic, 16)
     for (int i = 0; i < s->np; i++) {
         orc_particle *qi = &s->pt[i];
         for (int c = 0; c < 3; c++) { Fc[i][c] = 0; Tc[i][c] = 0; }
@@ -727,7 +743,7 @@ static void dem_substep(orc_state *s, double (*Fc)[3], double (*Tc)[3], orc_cont
                 hist[i][nh[i]].partner = jp;
                 memcpy(hist[i][nh[i]].xi, xn, sizeof xn);
                 nh[i]++;
-            } else s->error = 1;
+            } else overflow = 1;
         }
         /* Walls: halfway planes at -1/2 and n - 1/2 on non-periodic axes, same
          * material as the particles, R* = R_i. */
@@ -753,11 +769,13 @@ static void dem_substep(orc_state *s, double (*Fc)[3], double (*Tc)[3], orc_cont
                     hist[i][nh[i]].partner = partner;
                     memcpy(hist[i][nh[i]].xi, xn, sizeof xn);
                     nh[i]++;
-                } else s->error = 1;
+                } else overflow = 1;
             }
         }
     }
     free(list);
+    }
+    if (overflow) s->error = 1;
     /* Install the new histories (pairs no longer in contact are dropped). */
     for (int i = 0; i < s->np; i++) {
         s->pt[i].nc = nh[i];
@@ -829,6 +847,36 @@ void orc_step(orc_state *s, int nsteps)
         thermo(s);
         s->step++;
     }
+}
+
+/* One step of the one-point mode with prescribed reactions in place of the
+ * Lagrangian-point exchange (a learned closure supplies them): FH holds 4
+ * doubles per particle, the force F_p on the particle and the heat H_p it
+ * gives the fluid.  The fluid receives F_l A_l = -F_p and Q_l A_l = H_p
+ * spread from the centre (Eqs. lbm10-lbm12.6 for one point); the particle
+ * receives F_p and no fluid torque (a point has no lever arm, Eq. lbm13);
+ * the reactions record F_p, 0, H_p and sum (T_p - T_l) A = H_p / (2 kappa_T).
+ * Collision, DEM and the thermosensitive update follow as in orc_step. */
+void orc_step_prescribed(orc_state *s, const double *FH)
+{
+    stream(s);
+    moments(s);
+    memset(s->FB, 0, sizeof(double) * s->N * 3);
+    memset(s->QB, 0, sizeof(double) * s->N);
+    for (int ip = 0; ip < s->np; ip++) {
+        orc_particle *q = &s->pt[ip];
+        const double *r = FH + 4 * (long)ip;
+        double X[3] = {q->x[0], q->x[1], s->p.dim == 2 ? 0.0 : q->x[2]};
+        double FA[3] = {-r[0], -r[1], s->p.dim == 2 ? 0.0 : -r[2]};
+        spread_point(s, X, FA, r[3]);
+        for (int d = 0; d < 3; d++) { q->F[d] = -FA[d]; q->tq[d] = 0.0; }
+        q->H = r[3];
+        q->dTA = s->p.kappa_T != 0.0 ? r[3] / (2.0 * s->p.kappa_T) : 0.0;
+    }
+    collide(s);
+    dem(s);
+    thermo(s);
+    s->step++;
 }
 
 /* DEM only (no fluid): advance n_steps * n_sub sub-steps with the stored
@@ -911,6 +959,16 @@ void orc_totals(orc_state *s, double *out)
         r += s->rho[n]; jx += s->j[3*n]; jy += s->j[3*n+1]; jz += s->j[3*n+2]; t += s->S[n];
     }
     out[0] = r; out[1] = jx; out[2] = jy; out[3] = jz; out[4] = t;
+}
+
+/* Threads of the OpenMP loops from now on (n < 1: leave unchanged). */
+void orc_set_threads(int n)
+{
+#ifdef _OPENMP
+    if (n > 0) omp_set_num_threads(n);
+#else
+    (void)n;
+#endif
 }
 
 int orc_num_threads(void)

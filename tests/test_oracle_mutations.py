@@ -45,6 +45,10 @@ MUTANTS = [
      pins.test_interpolation_exact_for_linear_fields, dict(dim=2)),
     ("rigid_velocity_sign", "U[0] = q->u[0] + q->om[1]*r[2] - q->om[2]*r[1];",
      "U[0] = q->u[0] - q->om[1]*r[2] + q->om[2]*r[1];", pins.test_rotlet_torque_spinning_sphere, {}),
+    # the one-point step with prescribed reactions: the fluid takes -F
+    ("prescribed_force_sign", "double FA[3] = {-r[0], -r[1], s->p.dim == 2 ? 0.0 : -r[2]};",
+     "double FA[3] = {r[0], r[1], s->p.dim == 2 ? 0.0 : r[2]};", pins.test_prescribed_point_step_conserves_and_applies,
+     dict(dim=3)),
     # Eqs. (lbm7)-(lbm8): the exchange factor 2
     ("exchange_factor", "Fl[d] = 2.0 * (rl * U[d] - jl[d]);", "Fl[d] = (rl * U[d] - jl[d]);",
      pins.test_interpolation_exact_for_linear_fields, dict(dim=3)),

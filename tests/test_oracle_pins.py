@@ -498,6 +498,44 @@ def test_fixed_hot_body_heats_fluid_and_drag_opposes_motion(oracle_mod):
     assert o.totals()[4] > 0
 
 
+@pytest.mark.parametrize("dim", [2, 3])
+def test_prescribed_point_step_conserves_and_applies(oracle_mod, dim):
+    """The one-point step with prescribed reactions (the coarse mode's learned
+    closure): in a periodic box the fluid gains exactly -sum F_p of momentum
+    and sum H_p of heat (the kernel's partition of unity, Eq. lbm12, and the
+    Guo and heat sources, Eqs. lbm9, lbm12.5); the free particle gains F/m of
+    velocity, its centre moves by U0 + dts^2 F/m n(n + 1)/2 over n sub-steps,
+    the thermosensitive one cools by H / (rho_r c_r V); no fluid torque."""
+    mk = base2d if dim == 2 else base3d
+    cfg = mk(nx=20, ny=18, nz=16, T_init=0.3, T_ref=0.3, n_sub=3, c_r=1.4, marker_mode=2)
+    z = 7.2 if dim == 3 else 0.0
+    P = np.array([prow((5.3, 6.1, z), 0.6, 1.2, T=0.9, flags=W.FIXED, u=(0.01, 0, 0)),
+                  prow((13.6, 11.4, z), 0.7, 1.5, T=0.1, flags=W.THERMO, u=(0.002, -0.001, 0.003 if dim == 3 else 0))])
+    o = oracle_mod.Oracle(cfg, P)
+    o.step(4)                                      # a non-trivial state first
+    FH = np.array([[1e-3, -2e-3, 5e-4, 3e-3], [-4e-3, 1e-3, 2e-3 if dim == 3 else 0.0, -2e-3]])
+    if dim == 2:
+        FH[:, 2] = 0.0
+    t0, q0 = o.totals(), o.particles()
+    o.step_prescribed(FH)
+    t1, q1 = o.totals(), o.particles()
+    # round-off of sums over a few thousand nodes of values up to ~0.3
+    assert np.allclose(t1[1:4] - t0[1:4], -FH[:, :3].sum(0), rtol=0, atol=1e-13)
+    assert t1[4] - t0[4] == pytest.approx(FH[:, 3].sum(), abs=1e-13 * abs(t0[4]))
+    assert t1[0] == pytest.approx(t0[0], rel=1e-14)
+    r = o.reactions()
+    assert np.array_equal(r[:, :3], FH[:, :3]) and not r[:, 3:6].any() and np.array_equal(r[:, 6], FH[:, 3])
+    V = math.pi * 0.7 ** 2 if dim == 2 else 4.0 / 3.0 * math.pi * 0.7 ** 3
+    m = 1.5 * V
+    n, dts = 3, 1.0 / 3
+    assert np.allclose(q1[1, 3:6], q0[1, 3:6] + FH[1, :3] / m, rtol=1e-13, atol=1e-17)
+    expect_x = q0[1, 0:3] + q0[1, 3:6] + dts * dts * FH[1, :3] / m * n * (n + 1) / 2
+    assert np.allclose(q1[1, 0:3], expect_x, rtol=1e-13, atol=1e-13)
+    assert q1[1, 14] == pytest.approx(q0[1, 14] - FH[1, 3] / (1.5 * 1.4 * V), rel=1e-13)
+    assert np.array_equal(q1[0, :12], q0[0, :12])   # the fixed body does not move
+    assert not q1[:, 6:9].any()
+
+
 @pytest.mark.parametrize("d,rho_r", [(4.0, 1.01), (0.5, 1.01), (1.0, 2.5)])
 def test_point_particle_first_step_relaxation(oracle_mod, d, rho_r):
     """Eqs. (lbm7)-(lbm8), (lbm13) with A_p = pi d^2 / 4 (one point per
