@@ -15,6 +15,12 @@ def pytest_configure(config):
 
 @pytest.fixture(scope="session")
 def oracle_mod():
+    """The oracle module; PIBM_ORACLE_LIB names another build of the same
+    source to run the pins against (the sanitizer test uses it)."""
     from oracle import oracle as O
-    O.build()
+    alt = os.environ.get("PIBM_ORACLE_LIB")
+    if alt:
+        O._lib = O.load(alt)
+    else:
+        O.build()
     return O
