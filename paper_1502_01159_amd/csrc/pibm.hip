@@ -551,7 +551,7 @@ int launch_closure(pibm_ctx *c)
     hipLaunchKernelGGL((k_closure<DIM, T>), dim3((c->P.np + 127) / 128), dim3(128), 0, c->stream,
                        (const DevParticle *)c->r(c->pcur ? R_PART1 : R_PART0), c->P.np, (const float *)c->r(R_YMLP),
                        (const float *)c->r(R_NORM), (const float *)c->r(R_AUX), c->d.nu, c->d.alpha, c->p.kappa_T,
-                       (MarkerRec<T> *)c->r(R_MK), (DevReact *)c->r(R_REACT), (const int *)c->r(R_ERR));
+                       (MarkerRec<T> *)c->r(R_MK), (DevReact *)c->r(R_REACT), (int *)c->r(R_ERR));
     return hip_ok(c, hipGetLastError());
 }
 

@@ -169,6 +169,7 @@ __device__ __forceinline__ uint32_t sr_bits(uint32_t seed, int k)
 // --------------------------------------------------------------------------
 struct StF32 {
     using S = float; using T = float; using C = double;
+    static constexpr bool SCALED = false;     // stored deviation is f - w (not divided by w)
     static __device__ __forceinline__ T cvt(S v, double) { return v; }
     static __device__ __forceinline__ void st(S *p, T v, double) { *p = v; }
     static __device__ __forceinline__ void st_sum(S *p, T old, C inc, double, uint32_t r16)
@@ -181,6 +182,7 @@ struct StF32 {
 };
 struct StF64 {
     using S = double; using T = double; using C = double;
+    static constexpr bool SCALED = false;
     static __device__ __forceinline__ T cvt(S v, double) { return v; }
     static __device__ __forceinline__ void st(S *p, T v, double) { *p = v; }
     static __device__ __forceinline__ void st_sum(S *p, T old, C inc, double, uint32_t)
@@ -190,6 +192,7 @@ struct StF64 {
 };
 struct StF16 {
     using S = __half; using T = float; using C = float;
+    static constexpr bool SCALED = true;      // stored deviation is (f - w) / w
     static __device__ __forceinline__ T cvt(S v, double w) { return __half2float(v) * (float)w; }
     static __device__ __forceinline__ void st(S *p, T v, double w) { *p = __float2half_rn(v * (float)(1.0 / w)); }
     static __device__ __forceinline__ void st_sum(S *p, T old, C inc, double w, uint32_t r16)
@@ -204,6 +207,7 @@ struct StF16 {
 };
 struct StBF16 {
     using S = uint16_t; using T = float; using C = float;
+    static constexpr bool SCALED = true;
     static __device__ __forceinline__ T cvt(S v, double w) { return __uint_as_float(((uint32_t)v) << 16) * (float)w; }
     static __device__ __forceinline__ void st(S *p, T v, double w)
     {
@@ -263,6 +267,18 @@ __device__ __forceinline__ bool block_halted(const int *err)
     if (threadIdx.x == 0) s_halt = halted(err) ? 1 : 0;
     __syncthreads();
     return s_halt != 0;
+}
+
+// A particle centre that can be turned into lattice indices: finite and
+// within 1e8 of the origin.  Kernels that derive indices from a centre flag
+// any other state (ERR_DOMAIN) and skip the particle instead of converting
+// it: a float-to-int conversion of NaN or of a runaway value is undefined.
+__device__ __forceinline__ bool centre_ok(const DevParticle &P, int dim)
+{
+    bool ok = true;
+#pragma unroll
+    for (int d = 0; d < 3; ++d) ok = ok && (d >= dim || fabs(P.x[d]) < 1.0e8);   // constant indices
+    return ok;
 }
 
 constexpr int TILE_X = 64;
@@ -333,7 +349,10 @@ __device__ __forceinline__ S *addr_at(S *base, uint32_t elem)
     return (S *)((char *)base + (uint32_t)(elem * (uint32_t)sizeof(S)));
 }
 
-template <int DIM, class SF, class T, class TG>
+// RAW (lattice kernel, storage that divides the deviation by w): the values
+// are returned as stored, still divided by w, and the anti-bounce-back
+// Dirichlet value is divided by w too (w_q = w of the opposite direction).
+template <int DIM, class SF, class T, class TG, bool RAW = false>
 __device__ __forceinline__ void pull(const LbmArgs<T> &a, int x, int y, int z, T *f, TG *g)
 {
     using L = LatOf<DIM, SF>;
@@ -379,11 +398,11 @@ __device__ __forceinline__ void pull(const LbmArgs<T> &a, int x, int y, int z, T
     // every load of the node is issued before any value is used
     __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
-    for (int q = 0; q < L::Q; ++q) f[q] = SF::cvt(fr[q], L::w(q));
+    for (int q = 0; q < L::Q; ++q) f[q] = SF::cvt(fr[q], RAW ? 1.0 : L::w(q));
 #pragma unroll
     for (int q = 0; q < L::QG; ++q) {
-        const TG val = (TG)SF::cvt(gr[q], L::wg(q));
-        g[q] = gv[q] ? val : -val + (TG)(2.0 * L::wg(q) * a.tw[gface[q]]);
+        const TG val = (TG)SF::cvt(gr[q], RAW ? 1.0 : L::wg(q));
+        g[q] = gv[q] ? val : -val + (TG)(2.0 * (RAW ? 1.0 : L::wg(q)) * a.tw[gface[q]]);
     }
 }
 
@@ -482,12 +501,13 @@ __device__ __forceinline__ int spread_axis(int c, int n, int per)
     if (per) { c %= n; if (c < 0) c += n; }
     return c;
 }
-// Exclusive prefix sum over the wave of cnt (0 <= cnt < 32) and the total.
-__device__ __forceinline__ int wave_prefix5(int cnt, int &total)
+// Exclusive prefix sum over the wave of cnt (0 <= cnt < 2^BITS) and the total.
+template <int BITS>
+__device__ __forceinline__ int wave_prefix(int cnt, int &total)
 {
     int pre = 0, tot = 0;
 #pragma unroll
-    for (int bit = 0; bit < 5; ++bit) {
+    for (int bit = 0; bit < BITS; ++bit) {
         const unsigned long long bm = __ballot((cnt >> bit) & 1);
         pre += (int)__builtin_amdgcn_mbcnt_hi((unsigned)(bm >> 32), __builtin_amdgcn_mbcnt_lo((unsigned)bm, 0u)) << bit;
         tot += __popcll(bm) << bit;
@@ -514,7 +534,11 @@ __global__ __launch_bounds__(LBM_THREADS) void k_lbm(LbmArgs<typename SF::T> a)
     using L = LatOf<DIM, SF>;
     using TL = Tile<DIM>;
     constexpr int NC = DIM + 1;
-    constexpr int RMAX = DIM == 3 ? 16 : 4;          // footprint rows per point
+    // A point's footprint has 4 rows (fixed y) per z layer; each append
+    // queues the rows of one z layer (2D: its only layer), at most 4 per lane,
+    // and follows a drain to below 128 entries.  The small queue keeps the
+    // workgroup's LDS under 40 KB: four workgroups per CU.
+    constexpr int RMAX = 4;                           // rows appended per lane at a time
     constexpr int QCAP = 128 + 64 * RMAX;            // < 128 queued before each append
     constexpr int KSCAN = 4;                          // chunks whose loads are in flight together
     // fixed-point F_B, Q_B per tile node; rows (fixed y, z) padded to X + 1
@@ -615,24 +639,27 @@ __global__ __launch_bounds__(LBM_THREADS) void k_lbm(LbmArgs<typename SF::T> a)
                         zmask |= (lz >= 0 && lz < TL::Z) ? (1 << k) : 0;
                     }
                 }
-                cnt = xin ? __popc(ymask) * __popc(zmask) : 0;
+                cnt = xin ? __popc(ymask) : 0;        // rows per z layer
             }
-            int tot;
-            int pos = qn + wave_prefix5(cnt, tot);
-            if (cnt) {
+            // not unrolled: the drain below would be copied 16-fold into the scan's 4 unrolled calls
+#pragma unroll 1
+            for (int kz = 0; kz < (DIM == 3 ? 4 : 1); ++kz) {
+                const int c = ((zmask >> kz) & 1) ? cnt : 0;
+                int tot;
+                int pos = qn + wave_prefix<3>(c, tot);
+                if (c) {
 #pragma unroll
-                for (int ky = 0; ky < 4; ++ky)
-#pragma unroll
-                    for (int kz = 0; kz < (DIM == 3 ? 4 : 1); ++kz)
-                        if (((ymask >> ky) & (zmask >> kz) & 1) != 0) q[pos++] = (m << 4) | (ky << 2) | kz;
-            }
-            qn += tot;
-            __builtin_amdgcn_wave_barrier();
-            while (qn >= 128) {
-                qn -= 128;
-                const int ca = q[qn + lane], cb = q[qn + 64 + lane];
+                    for (int ky = 0; ky < 4; ++ky)
+                        if ((ymask >> ky) & 1) q[pos++] = (m << 4) | (ky << 2) | kz;
+                }
+                qn += tot;
                 __builtin_amdgcn_wave_barrier();
-                drain2(ca, true, cb, true);
+                while (qn >= 128) {
+                    qn -= 128;
+                    const int ca = q[qn + lane], cb = q[qn + 64 + lane];
+                    __builtin_amdgcn_wave_barrier();
+                    drain2(ca, true, cb, true);
+                }
             }
         };
 
@@ -714,29 +741,37 @@ __global__ __launch_bounds__(LBM_THREADS) void k_lbm(LbmArgs<typename SF::T> a)
                 else QB = v;
             }
         }
+        // 16-bit storage holds the deviation divided by w: the populations stay
+        // in that form (WF, WG = w when scaled, else 1), the moments take the
+        // weights in their sums, and the collision forms its increments
+        // divided by w (the weight factors out of every term of Eqs. lbm2,
+        // lbm3, lbm9 and lbm2.5, lbm12.5), so no value is multiplied by w on
+        // the way in or divided on the way out.
+        constexpr bool SC = SF::SCALED;
         T f[L::Q];
         C g[L::QG];
-        pull<DIM, SF, T, C>(a, x, y, z, f, g);
+        pull<DIM, SF, T, C, SC>(a, x, y, z, f, g);
         C fc[L::Q];
 #pragma unroll
         for (int q = 0; q < L::Q; ++q) fc[q] = (C)f[q];
         // raw moments rho - 1, j, S - T_ref, summed over opposite pairs
-        C drho = fc[0], j[3] = {0, 0, 0};
+        C drho = (C)(SC ? L::w(0) : 1.0) * fc[0], j[3] = {0, 0, 0};
 #pragma unroll
         for (int q = 1; q < L::Q; ++q) {
             const int o = L::opp(q);
             if (q > o) continue;
+            const C wq = (C)(SC ? L::w(q) : 1.0);
             const C sp = fc[q] + fc[o], dm = fc[q] - fc[o];
-            drho += sp;
+            drho += wq * sp;
 #pragma unroll
             for (int d = 0; d < DIM; ++d) {
-                if (L::e(q, d) > 0) j[d] += dm;
-                else if (L::e(q, d) < 0) j[d] -= dm;
+                if (L::e(q, d) > 0) j[d] += wq * dm;
+                else if (L::e(q, d) < 0) j[d] -= wq * dm;
             }
         }
         C dS = 0;
 #pragma unroll
-        for (int q = 0; q < L::QG; ++q) dS += g[q];
+        for (int q = 0; q < L::QG; ++q) dS += (C)(SC ? L::wg(q) : 1.0) * g[q];
         // Sec. 2.1 after Eq. (lbm3.5): T = S + Q_B / 2, u = (j + F / 2) / rho with
         // F = F_B + g beta (T - T_ref) e_up (buoyancy along +y in 2D, +z in 3D).
         const C rho = (C)1 + drho;
@@ -771,7 +806,8 @@ __global__ __launch_bounds__(LBM_THREADS) void k_lbm(LbmArgs<typename SF::T> a)
         //   P = w (K3 + e.u (9 gf e.F + 4.5 omega t)),  M = 3 w (gf e.F + omega t),
         //   K3 = omega (drho - 1.5 rho u.u) - 3 gf u.F.
         const C K3 = omf * (drho - (C)1.5 * rho * uu) - (C)3 * gf * uF;
-        SF::st_sum(addr_at(fb, n), f[0], (C)L::w(0) * K3 - omf * fc[0], L::w(0), SR ? sr_bits(seed, 0) : 0u);
+        SF::st_sum(addr_at(fb, n), f[0], (C)(SC ? 1.0 : L::w(0)) * K3 - omf * fc[0], SC ? 1.0 : L::w(0),
+                   SR ? sr_bits(seed, 0) : 0u);
 #pragma unroll
         for (int q = 1; q < L::Q; ++q) {
             const int o = L::opp(q);
@@ -782,16 +818,16 @@ __global__ __launch_bounds__(LBM_THREADS) void k_lbm(LbmArgs<typename SF::T> a)
                 if (L::e(q, d) > 0) { eu += u[d]; eF += F[d]; }
                 else if (L::e(q, d) < 0) { eu -= u[d]; eF -= F[d]; }
             }
-            const C wq = (C)L::w(q);
+            const C wq = (C)(SC ? 1.0 : L::w(q));
             const C t = rho * eu;
             const C ge = gf * eF;
             const C P = wq * (K3 + eu * ((C)9 * ge + (C)4.5 * omf * t));
             const C M = (C)3 * wq * (ge + omf * t);
             // both arrays of the pair from the pair's first one (q < o)
             S *pb = fb + (size_t)q * a.Ns;
-            SF::st_sum(addr_at(pb, n), f[q], (P + M) - omf * fc[q], L::w(q), SR ? sr_bits(seed, q) : 0u);
-            SF::st_sum(addr_at(pb, (uint32_t)(o - q) * (uint32_t)a.Ns + n), f[o], (P - M) - omf * fc[o], L::w(o),
-                       SR ? sr_bits(seed, o) : 0u);
+            SF::st_sum(addr_at(pb, n), f[q], (P + M) - omf * fc[q], SC ? 1.0 : L::w(q), SR ? sr_bits(seed, q) : 0u);
+            SF::st_sum(addr_at(pb, (uint32_t)(o - q) * (uint32_t)a.Ns + n), f[o], (P - M) - omf * fc[o],
+                       SC ? 1.0 : L::w(o), SR ? sr_bits(seed, o) : 0u);
         }
         // Thermal BGK with the linear equilibrium and the heat source
         // (Eqs. lbm2.5, lbm12.5): inc = w (gg Q_B + omega_g dT) +- omega_g w T e.u / c_sg^2 - omega_g g.
@@ -800,7 +836,8 @@ __global__ __launch_bounds__(LBM_THREADS) void k_lbm(LbmArgs<typename SF::T> a)
         const C Tabs = (C)a.Tref + dT;
         const C R = gg * QB + omg * dT + (L::QT ? -(C)1.5 * omg * Tabs * uu : (C)0);
         const C Z = omg * Tabs * (C)L::csg2_inv;
-        SF::st_sum(addr_at(gb, n), (T)g[0], (C)L::wg(0) * R - omg * g[0], L::wg(0), SR ? sr_bits(seed, L::Q) : 0u);
+        SF::st_sum(addr_at(gb, n), (T)g[0], (C)(SC ? 1.0 : L::wg(0)) * R - omg * g[0], SC ? 1.0 : L::wg(0),
+                   SR ? sr_bits(seed, L::Q) : 0u);
 #pragma unroll
         for (int q = 1; q < L::QG; ++q) {
             const int o = L::opp(q);
@@ -811,12 +848,13 @@ __global__ __launch_bounds__(LBM_THREADS) void k_lbm(LbmArgs<typename SF::T> a)
                 if (L::e(q, d) > 0) eu += u[d];
                 else if (L::e(q, d) < 0) eu -= u[d];
             }
-            const C wq = (C)L::wg(q);
+            const C wq = (C)(SC ? 1.0 : L::wg(q));
             const C P = wq * (L::QT ? R + (C)4.5 * omg * Tabs * eu * eu : R), M = wq * Z * eu;
             S *pb = gb + (size_t)q * a.Ns;
-            SF::st_sum(addr_at(pb, n), (T)g[q], (P + M) - omg * g[q], L::wg(q), SR ? sr_bits(seed, L::Q + q) : 0u);
-            SF::st_sum(addr_at(pb, (uint32_t)(o - q) * (uint32_t)a.Ns + n), (T)g[o], (P - M) - omg * g[o], L::wg(o),
-                       SR ? sr_bits(seed, L::Q + o) : 0u);
+            SF::st_sum(addr_at(pb, n), (T)g[q], (P + M) - omg * g[q], SC ? 1.0 : L::wg(q),
+                       SR ? sr_bits(seed, L::Q + q) : 0u);
+            SF::st_sum(addr_at(pb, (uint32_t)(o - q) * (uint32_t)a.Ns + n), (T)g[o], (P - M) - omg * g[o],
+                       SC ? 1.0 : L::wg(o), SR ? sr_bits(seed, L::Q + o) : 0u);
         }
     }
     if (bad) atomicOr(a.err, ERR_FIELD);
@@ -927,6 +965,10 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k
     const DevParticle P = a.part[p];
     const int m0 = a.mk_start[p], nm = a.mk_start[p + 1] - m0;
     if (block_halted(a.lb.err)) return;
+    if (!centre_ok(P, DIM)) {                      // uniform over the workgroup
+        if (tid == 0) atomicOr(a.lb.err, ERR_DOMAIN);
+        return;
+    }
     const int t0 = a.tmpl_start[P.tmpl];
     const int nn[3] = {a.lb.nx, a.lb.ny, a.lb.nz};
 
@@ -1134,6 +1176,7 @@ constexpr int FEAT_NB = 4;                      // neighbours kept (3D); 2D keep
 __device__ __forceinline__ int cell_coord(double x, int n, int per, int nc, double cw)
 {
     double y = x + 0.5;
+    if (!(fabs(y) < 1.0e9)) return 0;             // NaN / runaway: not converted (the DEM flags it)
     if (per) { y = fmod(y, (double)n); if (y < 0) y += n; }
     int c = (int)floor(y / cw);
     return c < 0 ? 0 : (c >= nc ? nc - 1 : c);
@@ -1191,6 +1234,10 @@ __global__ __launch_bounds__(FEAT_THREADS) void k_features(FeatArgs<typename SF:
     const int p = blockIdx.x, tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
     if (block_halted(a.lb.err)) return;
     const DevParticle P = a.part[p];
+    if (!centre_ok(P, DIM)) {                      // uniform over the workgroup
+        if (tid == 0) atomicOr(a.lb.err, ERR_DOMAIN);
+        return;
+    }
     const int nn[3] = {a.lb.nx, a.lb.ny, a.lb.nz};
     const double D = 2.0 * P.R;
     const double r_in = 0.75 * D, r_out = 1.5 * D, rphi = 2.0 * D;
@@ -1444,11 +1491,15 @@ __global__ void k_targets(const DevParticle *part, int np, const DevReact *react
 // no lever arm).
 template <int DIM, class T>
 __global__ void k_closure(const DevParticle *part, int np, const float *y, const float *norm, const float *aux,
-                          double nu, double alpha, double kappa, MarkerRec<T> *mk, DevReact *react, const int *err)
+                          double nu, double alpha, double kappa, MarkerRec<T> *mk, DevReact *react, int *err)
 {
     const int p = blockIdx.x * blockDim.x + threadIdx.x;
     if (p >= np || halted(err)) return;
     const DevParticle P = part[p];
+    if (!centre_ok(P, DIM)) {
+        atomicOr(err, ERR_DOMAIN);
+        return;
+    }
     double yv[4];
 #pragma unroll
     for (int q = 0; q < 4; ++q) yv[q] = (double)y[(size_t)p * 4 + q] * (double)norm[36 + q] + (double)norm[32 + q];
@@ -1539,10 +1590,7 @@ __device__ __forceinline__ void bin_particle(const BinArgs &a, int p, int lane)
     if (halted(a.err)) return;                     // uniform over the wave, as every early return here
     const DevParticle P = a.part[p];
     // a non-finite or runaway centre would give meaningless loop bounds
-    bool finite = true;
-#pragma unroll
-    for (int d = 0; d < 3; ++d) finite = finite && (d >= a.dim || fabs(P.x[d]) < 1.0e8);   // constant indices
-    if (!finite) {
+    if (!centre_ok(P, a.dim)) {
         if (!FILL && lane == 0) atomicOr(a.err, ERR_DOMAIN);
         return;
     }
