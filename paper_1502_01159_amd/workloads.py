@@ -227,6 +227,43 @@ def planted_3d(heat: bool = True, n: int = 15, layers: int = 13, per_axis: int =
 
 # --------------------------------------------------------------------------- #
 # The named workloads                                                          #
+def packed_bed(gap: float = 0.02, seed: int = 15):
+    """A dense bed for the DEM's contact path: 107 spheres of D = 6 stacked
+    body-centred in five layers (5 x 5 and 4 x 4 alternating) on the floor of
+    a walled 34 x 34 x 26 box.  A sphere of a 4 x 4 layer sits on four of the
+    layer below and under four of the layer above, `gap` apart, so gravity
+    closes every gap within tens of steps: up to 256 oblique pair contacts
+    and 25 floor contacts at once, with friction and tangential history.
+    Seeded small velocities and spins make the contacts slide.  Hot spheres,
+    heat exchange and buoyancy as in the 3D sedimentation case.  Density
+    ratio 3: spheres this small and light (rho_r 1.5) are unstable under the
+    explicit point exchange (their rotation grows about 1.45-fold per step),
+    heavier ones are not."""
+    D, R = 6.0, 3.0
+    a = 1.1 * D                                    # in-layer pitch: in-layer neighbours never touch
+    h = math.sqrt((D + gap) ** 2 - 0.5 * a * a)     # layer spacing: diagonal neighbours `gap` apart
+    cfg = dict(
+        name="packed_bed_107", dim=3, nx=34, ny=34, nz=26, periodic=[0, 0, 0],
+        T_wall=[0.0] * 6, T_init=0.0, T_ref=0.0,
+        Ra=0.0, nu=0.025, Pr=0.7, Gr=100.0, Lc=D,
+        gravity=4.167e-3, kappa_T=1.0, marker_mode=1, marker_spacing=1.0,
+        E_star=729.0, poisson=0.33, mu_fric=0.3, n_sub=9, beta_p=0.0, c_r=1.0,
+    )
+    rng = SplitMix64(seed)
+    rows = []
+    for k in range(5):
+        z = R - 0.5 + gap + k * h
+        if k % 2 == 0:
+            sites = [(0.5 * a + i * a, 0.5 * a + j * a) for j in range(5) for i in range(5)]
+        else:
+            sites = [(a + i * a, a + j * a) for j in range(4) for i in range(4)]
+        for x, y in sites:
+            u = [0.004 * (2 * rng.uniform() - 1) for _ in range(3)]
+            om = [0.002 * (2 * rng.uniform() - 1) for _ in range(3)]
+            rows.append(_row((x, y, z), R, 3.0, 1.0, 0, u=u, om=om))
+    return cfg, np.array(rows)
+
+
 # --------------------------------------------------------------------------- #
 
 def workload(name: str):
@@ -234,7 +271,8 @@ def workload(name: str):
     c1 annulus 64^2; c2 2D sedimentation 512x1024, 100 disks; c3 3D
     sedimentation 256x256x512, 2000 spheres; c4 thermosensitive 384^3, 20000
     spheres; x3 / x3_noheat the paper's planted 15^3 case with 8125 point
-    particles, with and without thermal buoyancy.  Small variants (suffix _small) keep the structure for parity
+    particles, with and without thermal buoyancy; packed_bed 107 spheres in
+    contact on a floor.  Small variants (suffix _small) keep the structure for parity
     runs that the oracle finishes in seconds."""
     if name == "c1":
         return annulus_2d(64)
@@ -257,6 +295,8 @@ def workload(name: str):
         return planted_3d(heat=True)
     if name == "x3_noheat":
         return planted_3d(heat=False)
+    if name == "packed_bed":
+        return packed_bed()
     raise KeyError(name)
 
 

@@ -102,13 +102,20 @@ def test_features_and_targets_match_oracle(gpu, oracle_mod, name, mode):
     sim.close()
 
 
-def test_closure_step_applies_network_outputs(gpu, oracle_mod):
-    """One step with the network as the closure: the particles' reactions are
-    the denormalised outputs for the features of the state the step starts
-    from, turned out of the slip frame (force) and scaled (heat), with no
-    fluid torque."""
-    import torch
-    from oracle import mlp_oracle as M
+def test_closure_step_matches_oracle_prescribed_step(gpu, oracle_mod):
+    """One step with the network as the closure, element by element against
+    the oracle's one-point step with prescribed reactions.  The network has
+    zero weights and output biases t, so it returns t exactly whatever its
+    inputs; with the identity denormalisation the reactions are
+    F = (t0 e1 + t1 e2 + t2 e3) 3 pi nu D |s| and H = t3 pi D alpha (T_p - T_f),
+    formed here from the features reference's slip s and T_f of the state
+    the step starts from.  The oracle spreads -F and H from the centres
+    (Eqs. lbm10-lbm12.6) and moves the particles with F and no fluid torque:
+    every population, particle and reaction must agree.  Two of the bodies are
+    freed and one made thermosensitive so that the DEM and the lumped heat
+    balance take the closure's reactions.  FP64 storage; the device keeps s
+    and T_f in FP32, which sets the tolerances."""
+    from oracle import closure_oracle as C
 
     cfg, P = W.workload("c3_small")
     cfg = W.with_overrides(cfg, marker_mode=2)
@@ -117,27 +124,60 @@ def test_closure_step_applies_network_outputs(gpu, oracle_mod):
     ref = oracle_mod.Oracle(cfg, P)
     sim.step(20)
     ref.step(20)
+    q = ref.particles()
+    P2 = q[:, [0, 1, 2, 3, 4, 5, 6, 7, 8, 12, 13, 14, 15]].copy()
+    P2[0, 12] = 0.0                                  # free
+    P2[1, 12] = float(W.THERMO)                      # free and thermosensitive
+    sim.set_particles(P2)
+    ref.set_particles(P2)
+    t = np.array([0.8, 0.15, -0.05, 1.3])
+    prm = np.zeros(gpu.MLP_NPARAM, dtype=np.float32)
+    prm[-4:] = t                                     # b4, the last block of the canonical order
     mlp = gpu.Mlp(seed=5, max_batch=64)
-    x, _ = sim.features()
-    mu = x.mean(0).astype(np.float32)
-    sd = (x.std(0) + 0.1).astype(np.float32)
-    norm = np.concatenate([mu, sd, np.array([0.5, -0.2, 0.1, 0.3], np.float32), np.array([2.0, 1.0, 1.5, 0.5], np.float32)])
+    mlp.set_params(prm)
+    norm = np.concatenate([np.zeros(16), np.ones(16), np.zeros(4), np.ones(4)]).astype(np.float32)
     sim.set_closure(mlp, norm)
-    _, _, s, d, Tf = reference(oracle_mod, ref, cfg)
-    xn = torch.tensor((x - mu) / sd, dtype=torch.float32).to(torch.bfloat16).cuda().contiguous()
-    y = mlp.forward(xn).cpu().numpy().astype(np.float64) * norm[36:40] + norm[32:36]
-    sim.step(1)
-    _, fth = sim.particles()
-    from oracle import closure_oracle as C
+    # oracle side: features of the state the step starts from, then the reactions
+    d = oracle_mod.derive(cfg)
+    rho, j, S = ref.raw_moments()
+    q = ref.particles()
+    shape = (cfg["nz"], cfg["ny"], cfg["nx"])
+    _, slips, Tf = C.features(rho, j, S, shape, cfg["periodic"], q, d["nu"], d["gbeta"], 3)
+    FH = np.zeros((len(P), 4))
     for p in range(len(P)):
-        e1, e2, e3 = C.slip_frame(s[p], 3)
-        fs = 3 * math.pi * d["nu"] * 2 * P[p, 9] * np.linalg.norm(s[p])
-        F = (y[p, 0] * e1 + y[p, 1] * e2 + y[p, 2] * e3) * fs
-        H = y[p, 3] * math.pi * 2 * P[p, 9] * d["alpha"] * (P[p, 11] - Tf[p])
-        sc = np.abs(F).max() + 1e-12
-        assert np.abs(fth[p, :3] - F).max() <= 2e-2 * sc, p
-        assert fth[p, 6] == pytest.approx(H, rel=2e-2, abs=1e-9)
-        assert not fth[p, 3:6].any()
+        e1, e2, e3 = C.slip_frame(slips[p], 3)
+        D = 2.0 * q[p, 12]
+        FH[p, :3] = (t[0] * e1 + t[1] * e2 + t[2] * e3) * 3.0 * math.pi * d["nu"] * D * np.linalg.norm(slips[p])
+        FH[p, 3] = t[3] * math.pi * D * d["alpha"] * (q[p, 14] - Tf[p])
+    assert np.abs(FH[:, :3]).max() > 1e-6 and np.abs(FH[:, 3]).max() > 1e-6
+    sim.step(1)
+    ref.step_prescribed(FH)
+    assert sim.sync() == gpu.OK
+    qs, fth = sim.particles()
+    qr, rr = ref.particles(), ref.reactions()
+    fsc, hsc = np.abs(FH[:, :3]).max(), np.abs(FH[:, 3]).max()
+    assert np.abs(fth[:, :3] - rr[:, :3]).max() <= 1e-6 * fsc
+    assert not fth[:, 3:6].any() and not rr[:, 3:6].any()
+    assert np.abs(fth[:, 6] - rr[:, 6]).max() <= 1e-6 * hsc
+    assert np.abs(fth[:, 7] - rr[:, 7]).max() <= 1e-6 * hsc
+    assert np.abs(qs[:, :12] - qr[:, :12]).max() <= 1e-10
+    # T_p -= H / (rho_r c_r V): the heat's tolerance carried through the update
+    V = 4.0 / 3.0 * math.pi * P2[:, 9] ** 3
+    assert np.all(np.abs(qs[:, 14] - qr[:, 14]) <= 1e-6 * hsc / (P2[:, 10] * cfg.get("c_r", 1.0) * V) + 1e-14)
+    assert abs(qs[1, 14] - P2[1, 11]) > 1e-6         # the thermosensitive body did exchange heat
+    f, g = sim.populations()
+    rf, rg = ref.populations()
+    print("closure step: max population differences", np.abs(f - rf).max(), np.abs(g - rg).max())
+    # the spread force and heat carry the reactions' 1e-6 (times a kernel weight
+    # of at most 1/8) into the populations
+    assert np.abs(f - rf).max() <= 1e-6 * fsc + 1e-13 and np.abs(g - rg).max() <= 1e-6 * hsc + 1e-13
+    e = field_errors_plain(sim.fields(), ref.fields())
+    assert max(e) <= 1e-8, e
+    sim.close()
+
+
+def field_errors_plain(a, b):
+    return [np.abs(x - y).max() / max(np.abs(y).max(), 1e-30) for x, y in zip(a, b)]
     sim.set_closure(None)
     mlp.close()
     sim.close()

@@ -172,37 +172,114 @@ def test_workloads_f32_1000_steps(gpu, oracle_mod, name, steps):
     assert dx <= 1e-4
 
 
-@pytest.mark.parametrize("storage,steps,bound", [("f64", 3, 1e-9), ("f32", 4, 1e-5)])
-def test_full_size_c3_every_node(gpu, oracle_mod, storage, steps, bound):
-    """The benchmark's default workload itself (256 x 256 x 512, 2000 spheres,
-    the two-stream step) against the oracle on every node and every particle
-    after a few steps: FP64 storage to the FP64 bar, FP32 to the FP32 bar."""
-    cfg, P = W.workload("c3")
-    sim, ref = run_pair(gpu, oracle_mod, cfg, P, steps, storage)
-    e = field_errors(sim.fields(), ref.fields())
-    print("c3", storage, steps, "steps: field errors", e)
-    assert max(e.values()) <= bound, e
+def _compare_full(gpu, ref, cfg, P, storage, steps, log):
+    """A fresh full-size run of `steps` steps in `storage` against the oracle
+    state `ref` (already at that step); returns per-field errors and the
+    largest position error."""
+    sim = gpu.Simulation(cfg, P, storage=storage)
+    sim.step(steps)
+    assert sim.sync() == gpu.OK
+    e = field_errors(sim.fields(), log["ref_fields"])
     q, fth = sim.particles()
+    dx = float(np.abs(q[:, :3] - ref.particles()[:, :3]).max())
+    print("c3", storage, steps, "steps: field errors", e, "max position error", dx, flush=True)
+    sim.close()
+    return e, dx, fth
+
+
+def test_full_size_c3_every_node(gpu, oracle_mod):
+    """The benchmark's default workload itself (256 x 256 x 512, 2000 spheres,
+    the two-stream step) against one oracle run on every node and particle:
+    FP64 storage after 3 steps to the FP64 bar; FP32, FP16 and BF16 deviation
+    storage after 4 steps (the variants the benchmark times); FP32 again
+    after 50 steps.  FP32: fields <= 1e-5, positions <= 1e-4 lu.  FP16: rho,
+    u and T <= 1e-3 of the FP64 result.  BF16 is reported (its 8-bit
+    significand misses the 1e-3 bar at longer horizons: see the small-box
+    test below) and bounded by 1e-2."""
+    cfg, P = W.workload("c3")
+    ref = oracle_mod.Oracle(cfg, P)
+    log = {}
+    ref.step(3)
+    log["ref_fields"] = ref.fields()
+    e, dx, fth = _compare_full(gpu, ref, cfg, P, "f64", 3, log)
+    assert max(e.values()) <= 1e-9 and dx <= 1e-10, e
+    reactions_close(fth, ref.reactions(), 1e-9, R=P[:, 9].max())
+    ref.step(1)
+    log["ref_fields"] = ref.fields()
+    results = {}
+    for storage in ("f32", "f16", "bf16"):
+        results[storage] = _compare_full(gpu, ref, cfg, P, storage, 4, log)[:2]
+    ref.step(46)
+    log["ref_fields"] = ref.fields()
+    results["f32_50"] = _compare_full(gpu, ref, cfg, P, "f32", 50, log)[:2]
+    for key, bound, dxb in (("f32", 1e-5, 1e-4), ("f32_50", 1e-5, 1e-4), ("f16", 1e-3, 1e-3), ("bf16", 1e-2, 1e-2)):
+        e, dx = results[key]
+        assert max(e.values()) <= bound and dx <= dxb, (key, e, dx)
+
+
+def test_full_size_c4_every_node(gpu, oracle_mod):
+    """The largest workload (384^3, 20,000 thermosensitive spheres, FP32
+    storage, the two-stream step) against the oracle on every node and every
+    particle after 3 steps: fields <= 1e-5, positions <= 1e-4 lu, particle
+    temperatures to 1e-5 of their range."""
+    cfg, P = W.workload("c4")
+    ref = oracle_mod.Oracle(cfg, P)
+    ref.step(3)
+    rf = ref.fields()
+    sim = gpu.Simulation(cfg, P, storage="f32")
+    sim.step(3)
+    assert sim.sync() == gpu.OK
+    e = field_errors(sim.fields(), rf)
+    q, _ = sim.particles()
     rq = ref.particles()
-    dx = np.abs(q[:, :3] - rq[:, :3]).max()
-    print("c3", storage, "max position error", dx)
-    assert dx <= (1e-10 if storage == "f64" else 1e-4)
-    if storage == "f64":
+    dx = float(np.abs(q[:, :3] - rq[:, :3]).max())
+    dT = float(np.abs(q[:, 14] - rq[:, 14]).max())
+    print("c4 f32 3 steps: field errors", e, "max position error", dx, "max particle T error", dT, flush=True)
+    assert max(e.values()) <= 1e-5, e
+    assert dx <= 1e-4 and dT <= 1e-5
+    sim.close()
+
+
+def test_packed_bed_contacts_f64(gpu, oracle_mod):
+    """The DEM's contact path under load: 107 spheres settling onto each
+    other and the floor (over 200 oblique pair contacts and 25 floor
+    contacts at once, counted from the oracle's brute-force contact lists,
+    with Coulomb-capped tangential springs), FP64 storage, 500 coupled steps
+    against the oracle: fields, positions, velocities, spins, reactions."""
+    cfg, P = W.workload("packed_bed")
+    sim = gpu.Simulation(cfg, P, storage="f64")
+    ref = oracle_mod.Oracle(cfg, P)
+    for chunk in range(2):
+        sim.step(250)
+        ref.step(250)
+        assert sim.sync() == gpu.OK
+        n_pairs = sum(len(ref.contacts(i)) for i in range(len(P))) // 2
+        q, fth = sim.particles()
+        rq = ref.particles()
+        dq = float(np.abs(q[:, :9] - rq[:, :9]).max())
+        print(f"packed bed {250 * (chunk + 1)} steps: {n_pairs} pair contacts, max state error {dq:.3e}", flush=True)
+        assert n_pairs >= 100
+        assert dq <= 1e-9
         reactions_close(fth, ref.reactions(), 1e-9, R=P[:, 9].max())
+    e = field_errors(sim.fields(), ref.fields())
+    assert max(e.values()) <= 1e-9, e
     sim.close()
 
 
 @pytest.mark.parametrize("storage,bound", [("f16", 1e-3), ("bf16", 1e-2)])
 def test_16bit_deviation_storage_error(gpu, oracle_mod, storage, bound):
     """FP16 / BF16 deviation storage collided in FP32: per-field error against
-    the FP64 oracle after 300 steps of the 3D sedimentation case."""
+    the FP64 oracle after 300 steps of the 3D sedimentation case.  FP16 meets
+    the 1e-3 bar on rho, u and T.  BF16's 8-bit significand does not: its u
+    and T errors are 3-5e-3 here, so its bound is 1e-2 and the miss is stated
+    wherever BF16 is reported."""
     cfg, P = W.workload("c3_small")
     sim, ref = run_pair(gpu, oracle_mod, cfg, P, 300, storage)
     e = field_errors(sim.fields(), ref.fields())
     q, _ = sim.particles()
     dx = np.abs(q[:, :3] - ref.particles()[:, :3]).max()
     print(storage, "field errors", e, "max position error", dx)
-    assert e["u"] <= bound and e["T"] <= bound, e
+    assert e["rho"] <= bound and e["u"] <= bound and e["T"] <= bound, e
 
 
 def test_bitwise_reproducible(gpu):
@@ -253,6 +330,39 @@ def test_watchdog_reports_runaway_velocity(gpu):
     assert s.sync() == gpu.EUNSTABLE
     with pytest.raises(gpu.PibmError):
         s.step(1)
+
+
+@pytest.mark.parametrize("streams", [1, 2])
+def test_nan_in_particle_stencil_reports_unstable(gpu, streams):
+    """Regression test of the recorded fault (non-finite particle centres gave
+    out-of-range indices).  NaN populations on a row through particle 0's
+    equator, inside the stencils of its Lagrangian points: the exchange gives
+    NaN reactions, the lattice kernel flags its NaN node, and the DEM either
+    stops at that flag (one stream) or, running beside the lattice kernel
+    (two streams), flags the NaN centre itself.  Every later kernel returns at
+    entry, pibm_sync reports PIBM_EUNSTABLE and the next pibm_step is refused;
+    the particle state is still readable and its reactions show that the NaN
+    went through the exchange."""
+    cfg, P = W.workload("c3_small")
+    s = gpu.Simulation(dict(cfg, streams=streams), P, storage="f32")
+    s.step(3)
+    assert s.sync() == gpu.OK
+    f, g = s.populations()
+    nx, ny = cfg["nx"], cfg["ny"]
+    x0, y0, z0, R = P[0, 0], P[0, 1], P[0, 2], P[0, 9]
+    j, k = int(math.floor(y0)), int(math.floor(z0))
+    for i in range(int(math.floor(x0 - R)) - 1, int(math.floor(x0 + R)) + 3):
+        f[3, (k * ny + j) * nx + i] = np.nan
+    print(f"NaN row through particle 0 (streams {streams})", flush=True)
+    s.set_populations(f, g)
+    s.step(2)
+    assert s.sync() == gpu.EUNSTABLE
+    with pytest.raises(gpu.PibmError):
+        s.step(1)
+    q, fth = s.particles(check=False)
+    assert not np.all(np.isfinite(fth[0]))          # the NaN went through the exchange
+    assert np.all(np.isfinite(fth[1:]))             # the other particles' stencils are clean
+    s.close()
 
 
 @pytest.mark.parametrize("case,storage", [("c3_small", "f32"), ("c2_small", "f16"), ("c4_small", "f32")])
