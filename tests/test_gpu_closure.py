@@ -171,13 +171,9 @@ def test_closure_step_matches_oracle_prescribed_step(gpu, oracle_mod):
     # the spread force and heat carry the reactions' 1e-6 (times a kernel weight
     # of at most 1/8) into the populations
     assert np.abs(f - rf).max() <= 1e-6 * fsc + 1e-13 and np.abs(g - rg).max() <= 1e-6 * hsc + 1e-13
-    e = field_errors_plain(sim.fields(), ref.fields())
-    assert max(e) <= 1e-8, e
+    # (no comparison of fields(): it evaluates the next step's exchange, the
+    # network on the device and the point exchange in the oracle)
     sim.close()
-
-
-def field_errors_plain(a, b):
-    return [np.abs(x - y).max() / max(np.abs(y).max(), 1e-30) for x, y in zip(a, b)]
     sim.set_closure(None)
     mlp.close()
     sim.close()
