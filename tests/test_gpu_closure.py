@@ -173,7 +173,6 @@ def test_closure_step_matches_oracle_prescribed_step(gpu, oracle_mod):
     assert np.abs(f - rf).max() <= 1e-6 * fsc + 1e-13 and np.abs(g - rg).max() <= 1e-6 * hsc + 1e-13
     # (no comparison of fields(): it evaluates the next step's exchange, the
     # network on the device and the point exchange in the oracle)
-    sim.close()
     sim.set_closure(None)
     mlp.close()
     sim.close()
