@@ -33,6 +33,9 @@ WORKLOAD_TEXT = {
     "c4": "3D thermosensitive spheres: D3Q19+D3Q7, 384^3, 20000 spheres D=10, Gr=100",
 }
 STORAGE_BYTES = {"f32": 4, "f64": 8, "f16": 2, "bf16": 2}
+# storage type of the populations and the type the collision computes in
+DTYPE_TEXT = {"f32": "f32 storage, f64 collision", "f64": "f64", "f16": "f16 storage, f32 collision",
+              "bf16": "bf16 storage, f32 collision"}
 
 
 def source_hash() -> str:
@@ -209,21 +212,107 @@ def mlp_variant(steps):
     return out
 
 
+def cpu_model() -> str:
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
 def cpu_baseline(cfg, P, steps):
+    """The FP64 oracle on the host cores: `steps` full coupled steps with all
+    threads, then one step with one thread (each after the same set-up)."""
     from oracle import oracle as O
 
     t0 = time.perf_counter()
     o = O.Oracle(cfg, P)
     t_init = time.perf_counter() - t0
+    threads = O.num_threads()
     t0 = time.perf_counter()
     o.step(steps)
     t = time.perf_counter() - t0
     n = o.N
+    O.set_threads(1)
+    t0 = time.perf_counter()
+    o.step(1)
+    t1 = time.perf_counter() - t0
+    O.set_threads(threads)
     del o
-    return dict(value=n * steps / t / 1e6, unit="MLUPS", cores=O.num_threads(), kind="oracle",
+    return dict(value=n * steps / t / 1e6, unit="MLUPS", cores=threads, kind="oracle",
                 sample=f"{steps} full coupled steps of the same workload ({n} nodes, {len(P)} particles), "
                        f"FP64, after {t_init:.1f} s of set-up",
-                seconds=round(t, 3))
+                seconds=round(t, 3),
+                single_thread=dict(value=round(n / t1 / 1e6, 3), unit="MLUPS", cores=1, seconds=round(t1, 3),
+                                   sample="1 further full coupled step of the same run, one thread"),
+                cpu_model=cpu_model(), nproc=os.cpu_count())
+
+
+def storage_errors(cfg, P, storages, steps):
+    """Field errors of each storage format against the FP64 path on the same
+    workload after `steps` steps (the FP64 path is held to 1e-9 of the FP64
+    oracle by the parity tests): max |a - b| / max |b| for rho, for u (all
+    components) and for T."""
+    import numpy as np
+    import torch
+
+    from paper_1502_01159_amd import pibm
+
+    def run(st):
+        sim = pibm.Simulation(cfg, P, storage=st)
+        sim.step(steps)
+        if sim.sync() != pibm.OK:
+            raise RuntimeError(f"watchdog in the {st} error run")
+        out = sim.fields()
+        sim.close()
+        del sim
+        torch.cuda.empty_cache()
+        return out
+
+    ref = run("f64")
+    errs = {}
+    for st in storages:
+        got = run(st)
+        errs[st] = {k: float(f"{np.abs(a - b).max() / max(np.abs(b).max(), 1e-30):.3e}")
+                    for k, a, b in zip(("rho", "u", "T"), got, ref)}
+        errs[st]["meets_1e-3"] = bool(errs[st]["u"] <= 1e-3 and errs[st]["T"] <= 1e-3)
+    return errs
+
+
+def graph_time(cfg, P, storage, steps, warmup):
+    """The step replayed from a HIP graph (timing only): two steps are captured
+    on a stream of their own (an even count returns every double buffer to
+    its place) and replayed.  The replays reuse the captured step counter, so
+    the stochastic-rounding stream repeats every two steps: the timing is
+    meaningful, the trajectory is not the eager one."""
+    import torch
+
+    from paper_1502_01159_amd import pibm
+
+    s = torch.cuda.Stream()
+    sim = pibm.Simulation(cfg, P, storage=storage, stream=s)
+    sim.step(warmup)
+    if sim.sync() != pibm.OK:
+        raise RuntimeError("watchdog before capture")
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g, stream=s):
+        sim.step(2)
+    torch.cuda.synchronize()
+    reps = max(steps // 2, 1)
+    with torch.cuda.stream(s):
+        g.replay()
+        ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        ev0.record(s)
+        for _ in range(reps):
+            g.replay()
+        ev1.record(s)
+    torch.cuda.synchronize()
+    ms = ev0.elapsed_time(ev1) / (2 * reps)
+    ok = sim.sync() == pibm.OK
+    sim.close()
+    return dict(ms_per_step=round(ms, 4), steps=2 * reps, watchdog_ok=ok)
 
 
 def main() -> int:
@@ -233,10 +322,14 @@ def main() -> int:
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--workload", default="c3", choices=sorted(WORKLOAD_TEXT))
     ap.add_argument("--storage", default="f32", choices=sorted(STORAGE_BYTES))
-    ap.add_argument("--variants", default="f16,bf16,q15,literal,mlp",
+    ap.add_argument("--variants", default="f16,bf16,q15,literal,c4,mlp",
                     help="extra storage formats timed beside the main one, 'q15' for the D3Q15 flow lattice "
                          "(FP32, 3D workloads), 'literal' for D3Q15 with temperature on the flow lattice "
-                         "(quadratic equilibrium, FP32) and 'mlp' for the learned part")
+                         "(quadratic equilibrium, FP32), 'c4' for the 384^3 thermosensitive workload (FP32) "
+                         "and 'mlp' for the learned part")
+    ap.add_argument("--error-steps", type=int, default=300,
+                    help="steps after which each storage format's fields are compared with the FP64 path (0: off)")
+    ap.add_argument("--graph", action="store_true", help="also time the step replayed from a HIP graph")
     ap.add_argument("--cpu-steps", type=int, default=4)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--empty", action="store_true", help="analysis: the same lattice without particles")
@@ -270,7 +363,7 @@ def main() -> int:
     phases = {k: round(v[0] / max(v[1], 1), 4) for k, v in main_run["all_prof"].items()}
 
     variants = {}
-    for st in [s for s in args.variants.split(",") if s and s != args.storage and s != "mlp"]:
+    for st in [s for s in args.variants.split(",") if s and s != args.storage and s not in ("mlp", "c4")]:
         if st in ("q15", "literal") and cfg["dim"] != 3:
             continue
         if st == "q15":
@@ -289,6 +382,27 @@ def main() -> int:
                             lattice_kernel_GBs=round(N * b / (lms * 1e-3 / max(ln, 1)) / 1e9, 1),
                             bytes_per_node=b)
 
+    if "c4" in args.variants.split(",") and args.workload == "c3" and not args.empty:
+        c4cfg, c4P = W.workload("c4")
+        n4 = max(args.steps // 2, 10)
+        r = time_gpu(c4cfg, c4P, "f32", n4, args.warmup)
+        lms, ln = r["prof"]["lattice"]
+        b = 2 * (r["Q"] + r["Qg"]) * STORAGE_BYTES["f32"]
+        gbs = r["N"] * b / (lms * 1e-3 / max(ln, 1)) / 1e9
+        variants["c4"] = dict(workload=WORKLOAD_TEXT["c4"], storage="f32",
+                              value=round(r["N"] * n4 / (r["ms"] * 1e-3) / 1e6, 1), unit="MLUPS",
+                              ms_per_step=round(r["ms"] / n4, 4), lattice_kernel_ms=round(lms / max(ln, 1), 4),
+                              lattice_kernel_GBs=round(gbs, 1), lattice_kernel_frac=round(gbs / HBM_PEAK_GBS, 4),
+                              bytes_per_node=b)
+    errs = None
+    err_st = [st for st in ("f32", "f16", "bf16") if st in args.variants.split(",") or st == args.storage]
+    if args.error_steps > 0 and err_st and not args.empty:
+        errs = storage_errors(cfg, P, err_st, args.error_steps)
+    graph = None
+    if args.graph or (args.workload == "c2" and not args.empty):
+        graph = graph_time(cfg, P, args.storage, args.steps, args.warmup)
+        graph["eager_ms_per_step"] = round(ms_step, 4)
+
     line = {
         "metric": METRIC,
         "value": round(mlups, 1),
@@ -300,7 +414,7 @@ def main() -> int:
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": args.storage,
+        "dtype": DTYPE_TEXT[args.storage],
         "data": "synthetic",
         "config": {"workload": WORKLOAD_TEXT[args.workload], "nodes": N, "particles": len(P),
                    "markers": main_run["markers"], "storage": args.storage, "n_sub": cfg["n_sub"],
@@ -326,6 +440,12 @@ def main() -> int:
                         "one stream: the phases run one after another")),
         "variants": variants,
     }
+    if errs is not None:
+        line["storage_error_vs_f64"] = dict(steps=args.error_steps, bar=1e-3, fields=errs,
+                                            note="fields after the same number of steps against the FP64 path "
+                                                 "on the same workload; the bar applies to u and T")
+    if graph is not None:
+        line["graph_replay"] = graph
     if "mlp" in [v for v in args.variants.split(",") if v]:
         line["mlp"] = mlp_variant(max(args.steps // 2, 10))
     if not args.no_copy_probe:

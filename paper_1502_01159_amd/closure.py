@@ -129,3 +129,83 @@ def run_states(pibm, cfg, P, times, storage="f32", mlp=None, norm=None):
         sim.set_closure(None)
     sim.close()
     return out
+
+
+def force_space_errors(Y, T, X):
+    """Relative L2 errors of predicted targets Y against T weighted back to
+    physical size: the force components times the slip (Re_p, column 0 of the
+    features), the Nusselt number times T_p - T_f (column 3).  Unlike errors
+    of the normalised targets, these are not dominated by samples with a
+    vanishing slip or temperature difference."""
+    eF = rel_l2(Y[:, :3] * X[:, :1], T[:, :3] * X[:, :1])
+    eH = rel_l2(Y[:, 3] * X[:, 3], T[:, 3] * X[:, 3])
+    return eF, eH
+
+
+def sedimentation_study(pibm, torch, steps=3800, every=20, start=500, epochs=60, re_min=0.05, coarse_steps=200,
+                        log=print):
+    """The closure at the scale of the 3D sedimentation case: samples every
+    `every` steps after `start` from the full 256 x 256 x 512 case with 2000
+    spheres at Gr = 0, 100 and 1000 (about 10^6), 10% of the particles held
+    out by id, GPU training, learning curves of the held-out and training
+    errors in force space, then the 4x coarser case (one point per sphere) with
+    the network and with the paper's point exchange, reporting the largest
+    particle speed and the watchdog status as the coarse runs advance."""
+    Xs, Ts, Is, Gs = [], [], [], []
+    for k, gr in enumerate((0, 100, 1000)):
+        cfg, P = W.workload(f"c3_gr{gr}")
+        X, T, ids, _ = harvest(pibm, cfg, P, steps=steps, every=every, start=start)
+        Xs.append(X); Ts.append(T); Is.append(ids + 10000 * k); Gs.append(np.full(len(X), gr))
+    X, T, I, G = map(np.concatenate, (Xs, Ts, Is, Gs))
+    ok = (X[:, 0] > re_min) & (np.abs(X[:, 3]) > 1e-3)
+    log(f"samples {len(X)}, usable {int(ok.sum())} (Re_p > {re_min}, |T_p - T_f| > 1e-3)")
+    X, T, I, G = X[ok], T[ok], I[ok], G[ok]
+    hold = (I % 10) == 0
+    norm = norm_stats(X[~hold], T[~hold])
+    mlp = pibm.Mlp(seed=7, max_batch=4096)
+    curve = []
+    for e0 in range(0, epochs, 5):
+        lr = 1e-3 if e0 < 2 * epochs // 3 else 3e-4
+        hist = train(torch, mlp, X[~hold], T[~hold], norm, epochs=5, batch=4096, lr=lr, seed=e0)
+        hF, hH = force_space_errors(predict(torch, mlp, X[hold], norm), T[hold], X[hold])
+        sub = np.nonzero(~hold)[0][:200000]
+        tF, tH = force_space_errors(predict(torch, mlp, X[sub], norm), T[sub], X[sub])
+        curve.append((e0 + 5, hist[-1], hF, hH, tF, tH))
+        log(f"epoch {e0 + 5}: loss {hist[-1]:.4f}  held-out force {hF:.3f} heat {hH:.3f}  "
+            f"training force {tF:.3f} heat {tH:.3f}")
+    per_gr = {}
+    for gr in (0, 100, 1000):
+        m = hold & (G == gr)
+        per_gr[gr] = force_space_errors(predict(torch, mlp, X[m], norm), T[m], X[m])
+        log(f"Gr {gr}: held-out force {per_gr[gr][0]:.3f} heat {per_gr[gr][1]:.3f}")
+    cfg, P = W.workload("c3_gr100")
+    cc, Pc = coarsen(cfg, P)
+    coarse = {}
+    for mode in ("network", "point exchange"):
+        sim = pibm.Simulation(cc, Pc, storage="f32")
+        if mode == "network":
+            sim.set_closure(mlp, norm)
+        trace = []
+        for k in range(0, coarse_steps, 10):
+            sim.step(10)
+            st = sim.sync()
+            q, _ = sim.particles(check=False)
+            trace.append((k + 10, st, float(np.abs(q[:, 3:6]).max())))
+            if st != pibm.OK:
+                break
+        log(f"coarse {mode}: " + ", ".join(f"step {a}: max|U_p| {c:.3f}" + ("" if b == pibm.OK else " (watchdog)")
+                                           for a, b, c in trace[::4] + ([trace[-1]] if len(trace) % 4 != 1 else [])))
+        coarse[mode] = trace
+        sim.set_closure(None)
+        sim.close()
+    mlp.close()
+    return dict(curve=curve, per_gr=per_gr, coarse=coarse)
+
+
+if __name__ == "__main__":
+    import torch
+
+    from . import pibm
+
+    sedimentation_study(pibm, torch)
+
