@@ -311,6 +311,17 @@ int pibm_features(pibm_ctx *ctx, float *x, float *t);
  * Eq. (lbm12).  m = NULL restores the point exchange. */
 int pibm_set_closure(pibm_ctx *ctx, pibm_mlp *m, const float *norm);
 
+/* Fallback of the learned closure to the method without it: lo[16], hi[16]
+ * (host, raw feature units as pibm_features returns them; +-infinity allowed,
+ * NaN refused) bound the inputs the network is trusted on.  Each step the
+ * point exchange of Sec. 2.2 (Eqs. lbm7-lbm8, lbm13) is evaluated for every
+ * particle, and the network's force and heat replace it only for particles
+ * whose 16 features all lie within [lo, hi] (a non-finite feature is outside).
+ * lo = hi = NULL removes the range (every particle takes the network);
+ * pibm_set_closure clears it.  PIBM_EINVAL without a closure set, or with
+ * only one of lo, hi.  Synchronises. */
+int pibm_set_closure_range(pibm_ctx *ctx, const float *lo, const float *hi);
+
 /* Static description of a status code. */
 const char *pibm_strerror(int status);
 

@@ -326,7 +326,7 @@ int make_plan(const pibm_params *p, const pibm_particle *pt, int np, Plan &P)
     sz[R_AUX] = npa * 4 * sizeof(float);
     sz[R_XBF] = npa * 16 * sizeof(uint16_t);
     sz[R_YMLP] = npa * 4 * sizeof(float);
-    sz[R_NORM] = 64 * sizeof(float);
+    sz[R_NORM] = 80 * sizeof(float);          // 40 normalisation values, then 16 + 16 range bounds
     sz[R_CNTR] = 64;                               // [0] tile items, [1] cell items
     sz[R_ERR] = 64;
     size_t o = 0;
@@ -426,6 +426,7 @@ struct pibm_ctx {
     int sticky;
     int device_lost;
     pibm_mlp *closure = nullptr;   // learned closure in the one-point mode (not owned)
+    bool closure_range = false;    // particles with features outside a range keep the point exchange
     // phase profiling: pairs of events recorded around each phase's launches
     unsigned prof_mask = 0;        // phases timed (bit 1 << PIBM_PHASE_*)
     std::vector<hipEvent_t> ev_free;
@@ -540,18 +541,24 @@ int launch_features(pibm_ctx *c, bool raw, bool for_network)
 
 // The learned closure in place of the Lagrangian-point exchange: features of
 // the current state, the network, and its outputs as point forces and heat.
+// With a feature range set, the point exchange runs first for every particle
+// and the closure replaces its record and reactions only where every feature
+// lies in the range.
 template <int DIM, class SF>
 int launch_closure(pibm_ctx *c)
 {
     using T = typename SF::T;
     if (c->P.np == 0) return PIBM_OK;
     int st;
-    if ((st = launch_features<DIM, SF>(c, false, true))) return st;
+    if (c->closure_range && (st = launch_markers<DIM, SF>(c, true))) return st;
+    if ((st = launch_features<DIM, SF>(c, c->closure_range, true))) return st;
     if ((st = pibm_mlp_forward_on(c->closure, c->r(R_XBF), (float *)c->r(R_YMLP), c->P.np, c->stream))) return st;
+    const float *norm = (const float *)c->r(R_NORM);
     hipLaunchKernelGGL((k_closure<DIM, T>), dim3((c->P.np + 127) / 128), dim3(128), 0, c->stream,
                        (const DevParticle *)c->r(c->pcur ? R_PART1 : R_PART0), c->P.np, (const float *)c->r(R_YMLP),
-                       (const float *)c->r(R_NORM), (const float *)c->r(R_AUX), c->d.nu, c->d.alpha, c->p.kappa_T,
-                       (MarkerRec<T> *)c->r(R_MK), (DevReact *)c->r(R_REACT), (int *)c->r(R_ERR));
+                       norm, (const float *)c->r(R_AUX), c->closure_range ? (const float *)c->r(R_FEAT) : nullptr,
+                       norm + 40, c->d.nu, c->d.alpha, c->p.kappa_T, (MarkerRec<T> *)c->r(R_MK),
+                       (DevReact *)c->r(R_REACT), (int *)c->r(R_ERR));
     return hip_ok(c, hipGetLastError());
 }
 
@@ -1124,7 +1131,7 @@ int pibm_set_closure(pibm_ctx *c, pibm_mlp *m, const float *norm)
 {
     if (!c) return PIBM_EINVAL;
     if (c->device_lost) return PIBM_EDEVICE;
-    if (!m) { c->closure = nullptr; return PIBM_OK; }
+    if (!m) { c->closure = nullptr; c->closure_range = false; return PIBM_OK; }
     if (c->p.marker_mode != PIBM_MARKERS_POINT || !norm) return PIBM_EINVAL;
     for (int i = 0; i < 40; ++i)
         if (!std::isfinite(norm[i])) return PIBM_EINVAL;
@@ -1136,6 +1143,26 @@ int pibm_set_closure(pibm_ctx *c, pibm_mlp *m, const float *norm)
     if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
     if (e != hipSuccess) return hip_ok(c, e);
     c->closure = m;
+    c->closure_range = false;
+    return PIBM_OK;
+}
+
+int pibm_set_closure_range(pibm_ctx *c, const float *lo, const float *hi)
+{
+    if (!c) return PIBM_EINVAL;
+    if (c->device_lost) return PIBM_EDEVICE;
+    if (!lo && !hi) { c->closure_range = false; return PIBM_OK; }
+    if (!c->closure || !lo || !hi) return PIBM_EINVAL;
+    float b[32];
+    for (int i = 0; i < 16; ++i) {
+        if (std::isnan(lo[i]) || std::isnan(hi[i])) return PIBM_EINVAL;
+        b[i] = lo[i];
+        b[16 + i] = hi[i];
+    }
+    hipError_t e = hipMemcpyAsync((float *)c->r(R_NORM) + 40, b, sizeof b, hipMemcpyHostToDevice, c->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    if (e != hipSuccess) return hip_ok(c, e);
+    c->closure_range = true;
     return PIBM_OK;
 }
 

@@ -1488,10 +1488,14 @@ __global__ void k_targets(const DevParticle *part, int np, const DevReact *react
 // (normalised targets) become the hydrodynamic force and heat of each
 // particle; its one point carries their reactions to the fluid (F_l A_l =
 // -F, Q_l A_l = H) and the DEM receives F and no fluid torque (a point has
-// no lever arm).
+// no lever arm).  With `feat` (the raw features) a particle takes the
+// network's values only when every feature lies in [range[i], range[16 + i]];
+// the others keep the point exchange of Sec. 2.2 (Eqs. lbm7-lbm8, lbm13),
+// which the caller ran for every particle before.
 template <int DIM, class T>
 __global__ void k_closure(const DevParticle *part, int np, const float *y, const float *norm, const float *aux,
-                          double nu, double alpha, double kappa, MarkerRec<T> *mk, DevReact *react, int *err)
+                          const float *feat, const float *range, double nu, double alpha, double kappa,
+                          MarkerRec<T> *mk, DevReact *react, int *err)
 {
     const int p = blockIdx.x * blockDim.x + threadIdx.x;
     if (p >= np || halted(err)) return;
@@ -1499,6 +1503,17 @@ __global__ void k_closure(const DevParticle *part, int np, const float *y, const
     if (!centre_ok(P, DIM)) {
         atomicOr(err, ERR_DOMAIN);
         return;
+    }
+    if (feat) {
+        // a feature outside the range (or not a number): the particle keeps
+        // the point exchange's record and reactions, written before
+        bool in = true;
+#pragma unroll
+        for (int i = 0; i < 16; ++i) {
+            const float v = feat[(size_t)p * 16 + i];
+            in = in && v >= range[i] && v <= range[16 + i];
+        }
+        if (!in) return;
     }
     double yv[4];
 #pragma unroll

@@ -27,7 +27,7 @@ EXPORTS = [
     "pibm_profile", "pibm_profile_phases", "pibm_profile_read",
     "pibm_mlp_workspace_bytes", "pibm_mlp_create", "pibm_mlp_set_params", "pibm_mlp_get_params",
     "pibm_mlp_forward", "pibm_mlp_grads", "pibm_mlp_train_step", "pibm_mlp_destroy",
-    "pibm_features", "pibm_set_closure", "pibm_mlp_grads_noalloc",
+    "pibm_features", "pibm_set_closure", "pibm_mlp_grads_noalloc", "pibm_set_closure_range",
 ]
 MLP_IN, MLP_HIDDEN, MLP_OUT, MLP_NPARAM = 16, 128, 4, 35716
 MLP_NOALLOC_MAX_BATCH = 4096
@@ -112,6 +112,7 @@ def lib():
         L.pibm_mlp_destroy.argtypes = [vp]
         L.pibm_features.argtypes = [vp, fp, fp]
         L.pibm_set_closure.argtypes = [vp, vp, fp]
+        L.pibm_set_closure_range.argtypes = [vp, fp, fp]
         _lib = L
     return _lib
 
@@ -294,6 +295,22 @@ class Simulation:
             st = lib().pibm_set_closure(self._h, mlp._h, norm.ctypes.data_as(ctypes.POINTER(ctypes.c_float)))
         if st != OK:
             raise PibmError(st, "pibm_set_closure")
+
+    def set_closure_range(self, lo, hi):
+        """Particles whose 16 raw features (as :meth:`features` returns them)
+        leave [lo, hi] keep the point exchange; None, None removes the range."""
+        fp = ctypes.POINTER(ctypes.c_float)
+        if lo is None and hi is None:
+            st = lib().pibm_set_closure_range(self._h, None, None)
+        else:
+            lo = np.ascontiguousarray(lo, dtype=np.float32)
+            hi = np.ascontiguousarray(hi, dtype=np.float32)
+            if lo.size != 16 or hi.size != 16:
+                raise ValueError("lo and hi must hold 16 values each")
+            self._range = (lo, hi)
+            st = lib().pibm_set_closure_range(self._h, lo.ctypes.data_as(fp), hi.ctypes.data_as(fp))
+        if st != OK:
+            raise PibmError(st, "pibm_set_closure_range")
 
     def fields(self, check: bool = True):
         rho = np.empty(self.N)

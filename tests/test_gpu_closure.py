@@ -208,6 +208,75 @@ def test_closure_two_streams_match_one_stream(gpu):
         assert np.array_equal(a, b)
 
 
+def test_closure_range_fallback_to_point_exchange(gpu):
+    """The closure's fallback to the method without it: with a feature range
+    set, a particle whose features leave the range keeps the point exchange
+    (Sec. 2.2, Eqs. lbm7-lbm8, lbm13) and the others take the network's
+    values.  Every run starts from the same state (20 point-exchange steps of
+    the heated spheres) and takes one step: a range holding every feature
+    gives the bits of the closure without a range, a range holding none the
+    bits of the point exchange, and a bound on Re_p between two particles'
+    values gives each particle the reactions of the run its Re_p selects."""
+    cfg, P = W.workload("c3_small")
+    cfg = W.with_overrides(cfg, marker_mode=2)
+    P = sub_grid(P)
+    mlp = gpu.Mlp(seed=5, max_batch=64)
+    probe = gpu.Simulation(cfg, P, storage="f32")
+    probe.step(20)
+    x, _ = probe.features()
+    probe.close()
+    mu = x.mean(0).astype(np.float32)
+    sd = (x.std(0) + 0.1).astype(np.float32)
+    norm = np.concatenate([mu, sd, np.array([0.5, -0.2, 0.1, 0.3], np.float32), np.array([2.0, 1.0, 1.5, 0.5], np.float32)])
+    inf = np.float32(np.inf)
+    re = np.sort(x[:, 0])
+    assert re[-1] > re[0] > 0
+    k = len(re) // 2
+    thr = np.float32(0.5 * (re[k - 1] + re[k]))
+    lo_mix, hi_mix = np.full(16, -inf, np.float32), np.full(16, inf, np.float32)
+    hi_mix[0] = thr
+
+    def run(closure, rng=None):
+        sim = gpu.Simulation(cfg, P, storage="f32")
+        sim.step(20)
+        if closure:
+            sim.set_closure(mlp, norm)
+            if rng is not None:
+                sim.set_closure_range(*rng)
+        sim.step(1)
+        assert sim.sync() == gpu.OK
+        f, g = sim.populations()
+        q, r = sim.particles()
+        sim.set_closure(None)
+        sim.close()
+        return f, g, q, r
+
+    point = run(False)
+    net = run(True)
+    every = run(True, (np.full(16, -inf, np.float32), np.full(16, inf, np.float32)))
+    none = run(True, (np.ones(16, np.float32), np.zeros(16, np.float32)))
+    mixed = run(True, (lo_mix, hi_mix))
+    assert not np.array_equal(point[3], net[3])
+    for a, b in zip(every, net):
+        assert np.array_equal(a, b)
+    for a, b in zip(none, point):
+        assert np.array_equal(a, b)
+    takes_net = x[:, 0] <= thr
+    assert 0 < takes_net.sum() < len(P)
+    assert np.array_equal(mixed[3][takes_net], net[3][takes_net])
+    assert np.array_equal(mixed[3][~takes_net], point[3][~takes_net])
+    # a range needs a closure, and both bounds
+    sim = gpu.Simulation(cfg, P, storage="f32")
+    with pytest.raises(gpu.PibmError):
+        sim.set_closure_range(lo_mix, hi_mix)
+    sim.set_closure(mlp, norm)
+    st = gpu.lib().pibm_set_closure_range(sim._h, lo_mix.ctypes.data_as(gpu.ctypes.POINTER(gpu.ctypes.c_float)), None)
+    assert st == gpu.EINVAL
+    sim.set_closure(None)
+    sim.close()
+    mlp.close()
+
+
 def test_learned_closure_beats_point_exchange(gpu):
     """What the network gains over the method without it.  Resolved runs of
     fixed hot spheres in a driven periodic box give samples; the network is
