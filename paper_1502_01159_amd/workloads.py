@@ -286,6 +286,11 @@ def workload(name: str):
             gr = float(name.split("_gr")[1])
         if name.startswith("c3_small"):
             return sediment_3d(nx=48, ny=40, nz=64, n_spheres=6, D=10.0, seed=13, Gr=gr)
+        if name.startswith("c3_mid"):
+            # the 256 x 256 x 512 case with a box 4 times smaller per axis and
+            # 32 spheres of the same D = 12 (the same solid fraction of about
+            # 0.17 in the seeded top third)
+            return sediment_3d(nx=64, ny=64, nz=128, n_spheres=32, D=12.0, seed=5, Gr=gr)
         return sediment_3d(Gr=gr)
     if name == "c4":
         return thermo_3d()
