@@ -149,8 +149,11 @@ def sedimentation_study(pibm, torch, steps=3800, every=20, start=500, epochs=60,
     spheres at Gr = 0, 100 and 1000 (about 10^6), 10% of the particles held
     out by id, GPU training, learning curves of the held-out and training
     errors in force space, then the 4x coarser case (one point per sphere) with
-    the network and with the paper's point exchange, reporting the largest
-    particle speed and the watchdog status as the coarse runs advance."""
+    the network, with the network and its fallback to the point exchange
+    outside the central 99% of each training feature, and with the paper's
+    point exchange alone, reporting the largest particle speed, the watchdog
+    status and the share of particles on the network as the coarse runs
+    advance."""
     Xs, Ts, Is, Gs = [], [], [], []
     for k, gr in enumerate((0, 100, 1000)):
         cfg, P = W.workload(f"c3_gr{gr}")
@@ -178,28 +181,40 @@ def sedimentation_study(pibm, torch, steps=3800, every=20, start=500, epochs=60,
         m = hold & (G == gr)
         per_gr[gr] = force_space_errors(predict(torch, mlp, X[m], norm), T[m], X[m])
         log(f"Gr {gr}: held-out force {per_gr[gr][0]:.3f} heat {per_gr[gr][1]:.3f}")
+    # the network is trusted on the central 99% of each training feature;
+    # outside it a particle falls back to the point exchange
+    lo = np.quantile(X[~hold], 0.005, axis=0).astype(np.float32)
+    hi = np.quantile(X[~hold], 0.995, axis=0).astype(np.float32)
     cfg, P = W.workload("c3_gr100")
     cc, Pc = coarsen(cfg, P)
     coarse = {}
-    for mode in ("network", "point exchange"):
+    for mode in ("network", "network with fallback", "point exchange"):
         sim = pibm.Simulation(cc, Pc, storage="f32")
-        if mode == "network":
+        if mode != "point exchange":
             sim.set_closure(mlp, norm)
+        if mode == "network with fallback":
+            sim.set_closure_range(lo, hi)
         trace = []
         for k in range(0, coarse_steps, 10):
             sim.step(10)
             st = sim.sync()
             q, _ = sim.particles(check=False)
-            trace.append((k + 10, st, float(np.abs(q[:, 3:6]).max())))
+            frac = float("nan")
+            if st == pibm.OK and mode == "network with fallback":
+                x, _ = sim.features()
+                frac = float(np.mean(np.all((x >= lo) & (x <= hi), axis=1)))
+            trace.append((k + 10, st, float(np.abs(q[:, 3:6]).max()), frac))
             if st != pibm.OK:
                 break
-        log(f"coarse {mode}: " + ", ".join(f"step {a}: max|U_p| {c:.3f}" + ("" if b == pibm.OK else " (watchdog)")
-                                           for a, b, c in trace[::4] + ([trace[-1]] if len(trace) % 4 != 1 else [])))
+        log(f"coarse {mode}: " + ", ".join(
+            f"step {a}: max|U_p| {c:.3f}" + ("" if b == pibm.OK else " (watchdog)") +
+            ("" if np.isnan(d) else f" on network {d:.2f}")
+            for a, b, c, d in trace[::4] + ([trace[-1]] if len(trace) % 4 != 1 else [])))
         coarse[mode] = trace
         sim.set_closure(None)
         sim.close()
     mlp.close()
-    return dict(curve=curve, per_gr=per_gr, coarse=coarse)
+    return dict(curve=curve, per_gr=per_gr, coarse=coarse, range=(lo, hi))
 
 
 if __name__ == "__main__":
