@@ -141,8 +141,10 @@ __host__ __device__ __forceinline__ uint32_t mix32(uint32_t x)
     x ^= x >> 16;
     return x;
 }
-// Sixteen random bits per stored value: one hash per node and step, and an
-// odd multiple of it per value (the high or low half of the product).
+// Sixteen random bits per stored value, in the top half of the returned
+// word: one hash per node and step, and an odd multiple of it per value (the
+// high or the low half of the product, the latter rotated up: a shift would
+// be folded into the multiply, which then runs at quarter rate).
 __device__ __forceinline__ uint32_t node_seed(uint32_t n, uint32_t step_seed)
 {
     return mix32(n * 0x9e3779b1u ^ step_seed);
@@ -151,7 +153,7 @@ __device__ __forceinline__ uint32_t sr_bits(uint32_t seed, int k)
 {
     // 24-bit product (full-rate multiply) of the seed with an odd constant
     const uint32_t P = __umul24(seed, ((uint32_t)(2 * (k >> 1) + 1) * 0x9e3779b1u) & 0xffffffu);
-    return (k & 1) ? (P & 0xffffu) : (P >> 16);
+    return (k & 1) ? __builtin_amdgcn_alignbit(P, P, 16) : P;
 }
 
 // --------------------------------------------------------------------------
@@ -172,11 +174,12 @@ struct StF32 {
     static constexpr bool SCALED = false;     // stored deviation is f - w (not divided by w)
     static __device__ __forceinline__ T cvt(S v, double) { return v; }
     static __device__ __forceinline__ void st(S *p, T v, double) { *p = v; }
-    static __device__ __forceinline__ void st_sum(S *p, T old, C inc, double, uint32_t r16)
+    static __device__ __forceinline__ void st_sum(S *p, T old, C inc, double, uint32_t rnd)
     {
-        // double -> float keeps 24 of 53 mantissa bits: randomise the 29 cut
+        // double -> float keeps 24 of 53 mantissa bits: randomise the top 16
+        // of the 29 cut
         unsigned long long b = (unsigned long long)__double_as_longlong((double)old + inc);
-        b = (b + ((unsigned long long)r16 << 13)) & ~0x1fffffffull;
+        b = (b + ((unsigned long long)(rnd >> 16) << 13)) & ~0x1fffffffull;
         __builtin_nontemporal_store((float)__longlong_as_double((long long)b), p);
     }
 };
@@ -190,19 +193,21 @@ struct StF64 {
         __builtin_nontemporal_store(old + inc, p);
     }
 };
+typedef __attribute__((ext_vector_type(2))) _Float16 h2x;   // the conversions' packed results
+typedef __attribute__((ext_vector_type(2))) __bf16 bf2x;
 struct StF16 {
     using S = __half; using T = float; using C = float;
     static constexpr bool SCALED = true;      // stored deviation is (f - w) / w
     static __device__ __forceinline__ T cvt(S v, double w) { return __half2float(v) * (float)w; }
     static __device__ __forceinline__ void st(S *p, T v, double w) { *p = __float2half_rn(v * (float)(1.0 / w)); }
-    static __device__ __forceinline__ void st_sum(S *p, T old, C inc, double w, uint32_t r16)
+    static __device__ __forceinline__ void st_sum(S *p, T old, C inc, double w, uint32_t rnd)
     {
-        // float -> half keeps 11 of 24 significant bits in the half's normal
-        // range: randomise the 13 cut, then the conversion is exact (below
-        // 2^-14 it rounds to nearest)
+        // gfx950's stochastic-rounding conversion: the top 13 bits of rnd are
+        // added below the half's 11 significant bits and the rest is cut
+        // (subnormal halves likewise; NaN and infinity kept)
         const float s = (old + inc) * (float)(1.0 / w);
-        const uint32_t b = (__float_as_uint(s) + (r16 >> 3)) & ~0x1fffu;
-        __builtin_nontemporal_store(__half_as_ushort(__float2half_rn(__uint_as_float(b))), (unsigned short *)p);
+        const h2x v = __builtin_amdgcn_cvt_sr_f16_f32(__builtin_bit_cast(h2x, rnd), s, rnd, false);   // high half unused
+        __builtin_nontemporal_store((unsigned short)(__builtin_bit_cast(uint32_t, v) & 0xffffu), (unsigned short *)p);
     }
 };
 struct StBF16 {
@@ -216,13 +221,13 @@ struct StBF16 {
         const uint32_t r = (u & 0x7fffffffu) > 0x7f800000u ? (u | 0x00400000u) : u + 0x7fffu + ((u >> 16) & 1u);
         *p = (uint16_t)(r >> 16);
     }
-    static __device__ __forceinline__ void st_sum(S *p, T old, C inc, double w, uint32_t r16)
+    static __device__ __forceinline__ void st_sum(S *p, T old, C inc, double w, uint32_t rnd)
     {
+        // stochastic-rounding conversion: the top 16 bits of rnd are added
+        // below the kept 8 significant bits and the rest is cut
         const float s = (old + inc) * (float)(1.0 / w);
-        const uint32_t u = __float_as_uint(s);
-        // NaN keeps a non-zero mantissa; otherwise randomise the 16 cut bits
-        const uint32_t r = (u & 0x7fffffffu) > 0x7f800000u ? (u | 0x00400000u) : u + r16;
-        __builtin_nontemporal_store((uint16_t)(r >> 16), p);
+        const bf2x v = __builtin_amdgcn_cvt_sr_bf16_f32(__builtin_bit_cast(bf2x, rnd), s, rnd, false);
+        __builtin_nontemporal_store((uint16_t)(__builtin_bit_cast(uint32_t, v) & 0xffffu), p);
     }
 };
 
@@ -778,7 +783,11 @@ __global__ __launch_bounds__(LBM_THREADS) void k_lbm(LbmArgs<typename SF::T> a)
         const C dT = dS + (C)0.5 * QB;
         C F[3] = {FB[0], FB[1], FB[2]};
         F[DIM - 1] += (C)a.gbeta * dT;
-        const C inv = (C)1 / rho;
+        // FP32 compute (16-bit storage): the hardware reciprocal (1 ulp) in
+        // place of the correctly rounded division sequence
+        C inv;
+        if constexpr (std::is_same<C, float>::value) inv = __builtin_amdgcn_rcpf(rho);
+        else inv = (C)1 / rho;
         C u[3] = {0, 0, 0};
 #pragma unroll
         for (int d = 0; d < DIM; ++d) u[d] = (j[d] + (C)0.5 * F[d]) * inv;
