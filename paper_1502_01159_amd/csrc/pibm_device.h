@@ -472,30 +472,38 @@ __device__ __forceinline__ int wrap_or_out(int c, int n, int per)
 // waves and list entries, with no atomics on floating point.
 // --------------------------------------------------------------------------
 // Fixed-point format of the spreading accumulators per point-record type.
-// FP32 records (FP32 / 16-bit storage): 2^-42 resolution, contributions
-// clamped to |v| <= 256 and rounded to nearest with the 1.5 * 2^52 shifter
-// (the integer lands in the low mantissa bits).  FP64 records (the parity
-// path): 2^-50 resolution, |v| <= 64, exact round-to-nearest conversion.
-// Either way a node holds thousands of maximal contributions before the
-// int64 sum could overflow; the clamp also maps NaN to a finite value, which
-// the node's velocity check then flags.
+// A contribution is a component v of a point record (clamped to |v| <= LIM,
+// which also maps NaN to a finite value that the node's velocity check then
+// flags) times the SCALE and one kernel weight w per axis.
+// FP32 records (FP32 / 16-bit storage): resolution 2^-36.  term() forms
+// v w + 1.5 2^52 in one FP64 FMA; the product of the two floats is exact, and
+// the sum's low 48 bits hold round(v w) in two's complement on top of the
+// shifter's bits, which lie above bit 47.  The accumulator adds these words
+// unchanged: the shifters pile up above bit 47 only, so the low 48 bits,
+// sign-extended once per node, are the exact sum while it stays below 2^47
+// (|F_B|, |Q_B| < 2048 at a node; a maximal contribution is 2^41, and any
+// state the watchdog lets run is orders of magnitude below).
+// FP64 records (the parity path): resolution 2^-50, |v| <= 64, exact
+// round-to-nearest conversion, int64 sums.
 template <class T> struct SpreadFix;
 template <> struct SpreadFix<float> {
-    static constexpr float SCALE = 0x1p42f, LIM = 256.0f;
-    static constexpr double INV = 0x1p-42;
-    static __device__ __forceinline__ unsigned long long fix(float scaled)
+    static constexpr float SCALE = 0x1p36f, LIM = 256.0f;
+    static __device__ __forceinline__ unsigned long long term(double v, double w)
     {
-        const double sh = 0x1.8p52;
-        return (unsigned long long)(__double_as_longlong((double)scaled + sh) - __double_as_longlong(sh));
+        return (unsigned long long)__double_as_longlong(fma(v, w, 0x1.8p52));
+    }
+    static __device__ __forceinline__ double value(unsigned long long a)
+    {
+        return (double)((long long)(a << 16) >> 16) * 0x1p-36;
     }
 };
 template <> struct SpreadFix<double> {
     static constexpr double SCALE = 0x1p50, LIM = 64.0;
-    static constexpr double INV = 0x1p-50;
-    static __device__ __forceinline__ unsigned long long fix(double scaled)
+    static __device__ __forceinline__ unsigned long long term(double v, double w)
     {
-        return (unsigned long long)(long long)rint(scaled);
+        return (unsigned long long)(long long)rint(v * w);
     }
+    static __device__ __forceinline__ double value(unsigned long long a) { return (double)(long long)a * 0x1p-50; }
 };
 
 // Node index on one axis: wrapped on periodic axes, unchanged otherwise (a
@@ -602,18 +610,19 @@ __global__ __launch_bounds__(LBM_THREADS) void k_lbm(LbmArgs<typename SF::T> a)
             const int lz = DIM == 3 ? spread_axis(r.b.z - 1 + r.kz, a.nz, a.per[2]) - z0 : 0;
             const int row = PXU * (ly + TL::Y * lz);
             const T wyz = r.wy * r.wz;
-            T v[NC];
+            double v[NC];
 #pragma unroll
             for (int c = 0; c < NC; ++c) {
                 const T cl = fmin(fmax(r.f[c], -SpreadFix<T>::LIM), SpreadFix<T>::LIM);   // NaN -> -limit
-                v[c] = cl * SpreadFix<T>::SCALE * wyz;
+                v[c] = (double)(cl * SpreadFix<T>::SCALE * wyz);
             }
 #pragma unroll
             for (int kx = 0; kx < 4; ++kx) {
                 const int lx = spread_axis(r.b.x - 1 + kx, a.nx, a.per[0]) - x0;
                 if (lx >= 0 && lx < TL::X) {
+                    const double wx = (double)r.w0[kx];
 #pragma unroll
-                    for (int c = 0; c < NC; ++c) atomicAdd(&acc[c][row + lx], SpreadFix<T>::fix(v[c] * r.w0[kx]));
+                    for (int c = 0; c < NC; ++c) atomicAdd(&acc[c][row + lx], SpreadFix<T>::term(v[c], wx));
                 }
             }
         };
@@ -741,7 +750,7 @@ __global__ __launch_bounds__(LBM_THREADS) void k_lbm(LbmArgs<typename SF::T> a)
         if (has) {
 #pragma unroll
             for (int c = 0; c < NC; ++c) {
-                const C v = (C)((double)(long long)acc[c][lr * PXU + lx] * SpreadFix<T>::INV);
+                const C v = (C)SpreadFix<T>::value(acc[c][lr * PXU + lx]);
                 if (c < DIM) FB[c] = v;
                 else QB = v;
             }
