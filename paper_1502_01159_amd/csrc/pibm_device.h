@@ -531,13 +531,25 @@ __device__ __forceinline__ int wave_prefix(int cnt, int &total)
 
 
 constexpr int XCD_CHUNK = 8;
+constexpr int TILE_STREAMS = 2;
 __device__ __forceinline__ int xcd_tile(int b, int G)
 {
     const int span = 8 * XCD_CHUNK;
     const int main = G - G % span;
     if (b >= main) return b;
     const int xcd = b & 7, slot = b >> 3;
-    return (slot / XCD_CHUNK) * span + xcd * XCD_CHUNK + slot % XCD_CHUNK;
+    // Groups of `span` consecutive tiles are dispatched from TILE_STREAMS
+    // contiguous parts of the domain in turn, each part in its own order:
+    // particles fill some regions only (the top third in sedimentation), and
+    // this keeps the workgroups that spread points beside ones that only
+    // stream, instead of leaving all spreading to one stretch of the launch.
+    const int NG = main / span, r = slot / XCD_CHUNK;
+    const int per = NG / TILE_STREAMS, extra = NG % TILE_STREAMS;
+    int part, i;
+    if (r < per * TILE_STREAMS) { part = r % TILE_STREAMS; i = r / TILE_STREAMS; }
+    else { part = r - per * TILE_STREAMS; i = per; }            // the longer parts' last groups
+    const int g = part * per + min(part, extra) + i;
+    return g * span + xcd * XCD_CHUNK + slot % XCD_CHUNK;
 }
 
 template <int DIM, class SF, bool MACRO>
