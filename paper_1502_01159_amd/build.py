@@ -13,6 +13,9 @@ HIPCC_FLAGS = [
     "-O3", "--offload-arch=gfx950", "-std=c++17", "-fPIC", "-shared",
     # no packed-FP32 instructions in any generated code
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+    # a name that hides another in an enclosing scope is an error (a spreading
+    # lambda once shadowed the tile origin)
+    "-Werror=shadow",
 ]
 
 

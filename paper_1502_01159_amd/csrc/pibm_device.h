@@ -243,13 +243,19 @@ struct DevParticle {               // 128 bytes, FP64
 struct DevReact {                  // per-particle reactions of the last step
     double F[3], tq[3], H, dTA;
 };
-template <typename T> struct alignas(16) MarkerRec {
+// A point record: 64 bytes with FP32 values (half a 128-byte line, never
+// straddling two) and 96 with FP64.  The cosine-kernel weights of one axis
+// pair up: delta(-1-t) + delta(1-t) = delta(-t) + delta(2-t) = 1/2 (Eq.
+// lbm12), so the record keeps those of nodes b-1 and b, and nodes b+1 and b+2
+// take 1/2 minus them (each axis's four weights sum to 1 by construction).
+template <typename T> struct alignas(sizeof(T) == 4 ? 64 : 32) MarkerRec {
     int b[3];                      // floor(X_l) per axis (unwrapped)
     int pad;
-    T w[3][4];                     // cosine-kernel weights of nodes b-1 .. b+2 per axis
+    T w[3][2];                     // cosine-kernel weights of nodes b-1 and b per axis
     T fa[3];                       // F_l A_l (force density times weight)
     T qa;                          // Q_l A_l
 };
+static_assert(sizeof(MarkerRec<float>) == 64 && sizeof(MarkerRec<double>) == 96, "point record sizes");
 
 enum : int {
     ERR_FIELD = 1,        // NaN / out-of-range rho or |u|
@@ -603,7 +609,7 @@ __global__ __launch_bounds__(LBM_THREADS) void k_lbm(LbmArgs<typename SF::T> a)
         // (3) a queued (point, row) entry: the row's nodes x = b-1 .. b+2.
         // fetch() only issues the loads, so that two batches are in flight
         // together; apply() adds the contributions.
-        struct Row { int4 b; T w0[4]; T wy, wz; T f[NC]; int ky, kz; };
+        struct Row { int4 b; T w[3][2]; T f[NC]; int ky, kz; };
         auto fetch = [&](int code, Row &r) {
             const int m = code >> 4;
             r.ky = (code >> 2) & 3;
@@ -611,9 +617,7 @@ __global__ __launch_bounds__(LBM_THREADS) void k_lbm(LbmArgs<typename SF::T> a)
             const MarkerRec<T> *R = a.mk + m;
             r.b = *(const int4 *)&R->b[0];
 #pragma unroll
-            for (int k = 0; k < 4; ++k) r.w0[k] = R->w[0][k];
-            r.wy = R->w[1][r.ky];
-            r.wz = DIM == 3 ? R->w[2][r.kz] : (T)1;
+            for (int d = 0; d < DIM; ++d) { r.w[d][0] = R->w[d][0]; r.w[d][1] = R->w[d][1]; }
 #pragma unroll
             for (int c = 0; c < NC; ++c) r.f[c] = c < DIM ? R->fa[c] : R->qa;
         };
@@ -621,7 +625,17 @@ __global__ __launch_bounds__(LBM_THREADS) void k_lbm(LbmArgs<typename SF::T> a)
             const int ly = spread_axis(r.b.y - 1 + r.ky, a.ny, a.per[1]) - y0;
             const int lz = DIM == 3 ? spread_axis(r.b.z - 1 + r.kz, a.nz, a.per[2]) - z0 : 0;
             const int row = PXU * (ly + TL::Y * lz);
-            const T wyz = r.wy * r.wz;
+            // the axis weights of nodes b-1 .. b+2: w0, w1, 1/2 - w0, 1/2 - w1
+            const T wa = r.w[0][0], wb = r.w[0][1];
+            const T w0[4] = {wa, wb, (T)0.5 - wa, (T)0.5 - wb};
+            const T yk = (r.ky & 1) ? r.w[1][1] : r.w[1][0];
+            const T wy = r.ky < 2 ? yk : (T)0.5 - yk;
+            T wz = (T)1;
+            if (DIM == 3) {
+                const T zk = (r.kz & 1) ? r.w[2][1] : r.w[2][0];
+                wz = r.kz < 2 ? zk : (T)0.5 - zk;
+            }
+            const T wyz = wy * wz;
             double v[NC];
 #pragma unroll
             for (int c = 0; c < NC; ++c) {
@@ -632,7 +646,7 @@ __global__ __launch_bounds__(LBM_THREADS) void k_lbm(LbmArgs<typename SF::T> a)
             for (int kx = 0; kx < 4; ++kx) {
                 const int lx = spread_axis(r.b.x - 1 + kx, a.nx, a.per[0]) - x0;
                 if (lx >= 0 && lx < TL::X) {
-                    const double wx = (double)r.w0[kx];
+                    const double wx = (double)w0[kx];
 #pragma unroll
                     for (int c = 0; c < NC; ++c) atomicAdd(&acc[c][row + lx], SpreadFix<T>::term(v[c], wx));
                 }
@@ -829,11 +843,11 @@ __global__ __launch_bounds__(LBM_THREADS) void k_lbm(LbmArgs<typename SF::T> a)
         S *fb = (S *)a.fB;
         S *gb = (S *)a.gB;
         // Forced BGK (Eqs. lbm2, lbm3, lbm9) as increments f* - f = src - omega (f - f^eq)
-        // over opposite pairs q, q' = -q.  With t = rho e.u, f^eq - w has the
-        // even part w (drho - 1.5 rho u.u + 4.5 t e.u) and the odd part 3 w t;
+        // over opposite pairs q, q' = -q.  With te = rho e.u, f^eq - w has the
+        // even part w (drho - 1.5 rho u.u + 4.5 te e.u) and the odd part 3 w te;
         // the source has the even part w gf (9 e.u e.F - 3 u.F) and the odd
         // part 3 w gf e.F.  So inc(q, q') = P +- M - omega f with
-        //   P = w (K3 + e.u (9 gf e.F + 4.5 omega t)),  M = 3 w (gf e.F + omega t),
+        //   P = w (K3 + e.u (9 gf e.F + 4.5 omega te)),  M = 3 w (gf e.F + omega te),
         //   K3 = omega (drho - 1.5 rho u.u) - 3 gf u.F.
         const C K3 = omf * (drho - (C)1.5 * rho * uu) - (C)3 * gf * uF;
         SF::st_sum(addr_at(fb, n), f[0], (C)(SC ? 1.0 : L::w(0)) * K3 - omf * fc[0], SC ? 1.0 : L::w(0),
@@ -849,10 +863,10 @@ __global__ __launch_bounds__(LBM_THREADS) void k_lbm(LbmArgs<typename SF::T> a)
                 else if (L::e(q, d) < 0) { eu -= u[d]; eF -= F[d]; }
             }
             const C wq = (C)(SC ? 1.0 : L::w(q));
-            const C t = rho * eu;
+            const C te = rho * eu;
             const C ge = gf * eF;
-            const C P = wq * (K3 + eu * ((C)9 * ge + (C)4.5 * omf * t));
-            const C M = (C)3 * wq * (ge + omf * t);
+            const C P = wq * (K3 + eu * ((C)9 * ge + (C)4.5 * omf * te));
+            const C M = (C)3 * wq * (ge + omf * te);
             // both arrays of the pair from the pair's first one (q < o)
             S *pb = fb + (size_t)q * a.Ns;
             SF::st_sum(addr_at(pb, n), f[q], (P + M) - omf * fc[q], SC ? 1.0 : L::w(q), SR ? sr_bits(seed, q) : 0u);
@@ -940,11 +954,11 @@ __device__ __forceinline__ void marker_setup(const DevParticle &P, const double4
             tt[d] = X - fl;
             double wk[4];
             cos_weights(tt[d], wk);
-#pragma unroll
-            for (int k = 0; k < 4; ++k) rec.w[d][k] = (T)wk[k];
+            rec.w[d][0] = (T)wk[0];
+            rec.w[d][1] = (T)wk[1];
         } else {
             rec.b[d] = 0; tt[d] = 0;
-            rec.w[d][0] = (T)1; rec.w[d][1] = rec.w[d][2] = rec.w[d][3] = (T)0;
+            rec.w[d][0] = (T)1; rec.w[d][1] = (T)0;      // unused (2D)
         }
     }
 }
