@@ -44,12 +44,16 @@ typedef enum {
 } pibm_status;
 
 /* Storage of the distributions.  Every variant stores deviations from the
- * rest state (f - w rho0, g - w T_ref) and collides in a compute type:
+ * rest state (f - w rho0, g - w T_s) and collides in a compute type:
  * F32 stores float and collides in double, rounding the stored deviations
  * stochastically (a counter hash of node, population and step decides the
  * rounding direction, so runs are reproducible); F64 stores and collides in
  * double; F16DEV / BF16DEV store 16-bit deviations scaled by 1/w, collide in
- * float and round stochastically the same way. */
+ * float and round stochastically the same way.  T_s = T_ref, except for the
+ * 16-bit variants: there T_s is the middle of the temperatures the case sets
+ * at pibm_init (T_init, the walls of non-periodic axes, the particles), so the
+ * stored values keep the finest spacing.  Populations exchanged through
+ * pibm_get_populations / pibm_set_populations are absolute either way. */
 typedef enum {
     PIBM_STORE_F32 = 0,
     PIBM_STORE_F64 = 1,

@@ -407,6 +407,11 @@ struct pibm_ctx {
     Plan P;
     Derived d;
     hipStream_t stream;
+    // Temperature the g deviations are stored from: T_ref, except with 16-bit
+    // storage, where it is the middle of the temperatures the case sets at
+    // the start (fluid, walls, particles), so that the stored (g - w T_s) / w
+    // stay within half the temperature range and keep the finest spacing.
+    double T_store = 0.0;
     // Second stream on the same device: binning runs beside the marker
     // kernel and the DEM sub-steps beside the lattice kernel.  Each step forks
     // from `stream` and joins back into it, so all work stays ordered with
@@ -454,8 +459,9 @@ template <class T> LbmArgs<T> lbm_args(const pibm_ctx *c)
     a.gf = 1.0 - 0.5 / c->d.tau_f;
     a.gg = 1.0 - 0.5 / c->d.tau_g;
     a.gbeta = c->d.gbeta;
-    a.Tref = c->p.T_ref;
-    for (int k = 0; k < 6; ++k) a.tw[k] = c->p.T_wall[k] - c->p.T_ref;
+    a.Tref = c->T_store;
+    a.dTb = c->T_store - c->p.T_ref;
+    for (int k = 0; k < 6; ++k) a.tw[k] = c->p.T_wall[k] - c->T_store;
     const int src = c->cur;
     a.fA = c->r(src ? R_FB : R_FA);
     a.gA = c->r(src ? R_GB : R_GA);
@@ -504,7 +510,7 @@ int launch_markers(pibm_ctx *c, bool reactions)
     m.mk = (MarkerRec<T> *)c->r(R_MK);
     m.react = reactions ? (DevReact *)c->r(R_REACT) : nullptr;
     m.kappa = c->p.kappa_T;
-    m.Tref = c->p.T_ref;
+    m.Tref = c->T_store;
     if (c->p.interp_order == 4)
         hipLaunchKernelGGL((k_markers<DIM, SF, 4>), dim3(c->P.np), dim3(256), 0, c->stream, m);
     else
@@ -869,7 +875,7 @@ template <int DIM, class SF> struct InitOp {
         using T = typename SF::T;
         const int g = (int)std::min<long long>(4096, (c->P.N + 255) / 256);
         hipLaunchKernelGGL((k_init<SF, LatOf<DIM, SF>>), dim3(g), dim3(256), 0, c->stream, c->r(R_FA), c->r(R_GA),
-                           c->P.N, c->P.Ns, (T)(c->p.T_init - c->p.T_ref));
+                           c->P.N, c->P.Ns, (T)(c->p.T_init - c->T_store));
         return hip_ok(c, hipGetLastError());
     }
 };
@@ -981,6 +987,14 @@ int pibm_init(pibm_ctx **out, const pibm_params *p, const pibm_particle *pt, int
     if (st != PIBM_OK) { delete c; return st; }
     c->p = *p;
     c->d = derive(*p);
+    c->T_store = p->T_ref;
+    if (p->storage == PIBM_STORE_F16DEV || p->storage == PIBM_STORE_BF16DEV) {
+        double lo = p->T_init, hi = p->T_init;
+        for (int f = 0; f < 2 * p->dim; ++f)
+            if (!p->periodic[f / 2]) { lo = std::min(lo, p->T_wall[f]); hi = std::max(hi, p->T_wall[f]); }
+        for (int i = 0; i < n; ++i) { lo = std::min(lo, pt[i].T); hi = std::max(hi, pt[i].T); }
+        c->T_store = 0.5 * (lo + hi);
+    }
     c->stream = (hipStream_t)stream;
     c->ws = (char *)ws;
     c->ws_bytes = ws_bytes;
@@ -1182,7 +1196,7 @@ int pibm_get_populations(pibm_ctx *c, double *f, double *g)
         for (size_t n = 0; n < N; ++n) f[q * N + n] = wf(dim, c->p.lattice, q) + stored_to_dev(c, hf.data(), q * Ns + n, wf(dim, c->p.lattice, q));
     for (int q = 0; q < QG; ++q)
         for (size_t n = 0; n < N; ++n)
-            g[q * N + n] = wgt(dim, c->p.lattice, c->p.thermal_model, q) * c->p.T_ref + stored_to_dev(c, hg.data(), q * Ns + n, wgt(dim, c->p.lattice, c->p.thermal_model, q));
+            g[q * N + n] = wgt(dim, c->p.lattice, c->p.thermal_model, q) * c->T_store + stored_to_dev(c, hg.data(), q * Ns + n, wgt(dim, c->p.lattice, c->p.thermal_model, q));
     return st;
 }
 
@@ -1197,7 +1211,7 @@ int pibm_set_populations(pibm_ctx *c, const double *f, const double *g)
         for (size_t n = 0; n < N; ++n) dev_to_stored(c, hf.data(), q * Ns + n, f[q * N + n] - wf(dim, c->p.lattice, q), wf(dim, c->p.lattice, q));
     for (int q = 0; q < QG; ++q)
         for (size_t n = 0; n < N; ++n)
-            dev_to_stored(c, hg.data(), q * Ns + n, g[q * N + n] - wgt(dim, c->p.lattice, c->p.thermal_model, q) * c->p.T_ref, wgt(dim, c->p.lattice, c->p.thermal_model, q));
+            dev_to_stored(c, hg.data(), q * Ns + n, g[q * N + n] - wgt(dim, c->p.lattice, c->p.thermal_model, q) * c->T_store, wgt(dim, c->p.lattice, c->p.thermal_model, q));
     hipError_t e = hipMemcpyAsync(c->r(c->cur ? R_FB : R_FA), hf.data(), hf.size(), hipMemcpyHostToDevice, c->stream);
     if (e == hipSuccess) e = hipMemcpyAsync(c->r(c->cur ? R_GB : R_GA), hg.data(), hg.size(), hipMemcpyHostToDevice, c->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
@@ -1224,6 +1238,7 @@ struct BlobHeader {
     long long step;
     pibm_params p;
     long long N, np;
+    double T_store;                // the populations' g offset (pibm_ctx::T_store)
 };
 const int blob_regions[] = {R_FA, R_GA, R_FB, R_GB, R_PART0, R_PART1, R_REACT, R_HID0, R_HXI0, R_HN0, R_HID1, R_HXI1, R_HN1};
 }
@@ -1238,7 +1253,8 @@ int pibm_save(pibm_ctx *c, void *buf, size_t cap, size_t *used)
     if (cap < total) return PIBM_EINVAL;
     BlobHeader h{};
     std::memcpy(h.magic, "PIBMCKP", 8);
-    h.version = 1; h.cur = c->cur; h.pcur = c->pcur; h.hcur = c->hcur; h.step = c->step; h.p = c->p;
+    h.version = 2; h.cur = c->cur; h.pcur = c->pcur; h.hcur = c->hcur; h.step = c->step; h.p = c->p;
+    h.T_store = c->T_store;
     h.N = c->P.N; h.np = c->P.np;
     std::memcpy(buf, &h, sizeof h);
     char *o = (char *)buf + sizeof h;
@@ -1256,7 +1272,7 @@ int pibm_load(pibm_ctx *c, const void *buf, size_t n)
     if (!c || !buf || n < sizeof(BlobHeader)) return PIBM_EINVAL;
     BlobHeader h;
     std::memcpy(&h, buf, sizeof h);
-    if (std::memcmp(h.magic, "PIBMCKP", 8) != 0 || h.version != 1) return PIBM_ESTATE;
+    if (std::memcmp(h.magic, "PIBMCKP", 8) != 0 || h.version != 2) return PIBM_ESTATE;
     if (std::memcmp(&h.p, &c->p, sizeof(pibm_params)) != 0 || h.N != c->P.N || h.np != c->P.np) return PIBM_ESTATE;
     size_t total = sizeof(BlobHeader);
     for (int r : blob_regions) total += c->P.off[r + 1] - c->P.off[r];
@@ -1269,6 +1285,7 @@ int pibm_load(pibm_ctx *c, const void *buf, size_t n)
         o += b;
     }
     c->cur = h.cur; c->pcur = h.pcur; c->hcur = h.hcur; c->step = h.step; c->cells_ok = 0; c->tiles_next = 0;
+    c->T_store = h.T_store;
     return hip_ok(c, hipStreamSynchronize(c->stream));
 }
 

@@ -13,8 +13,9 @@
 // Data layout in HBM: structure of arrays, population q of node n at
 // q * Ns + n, n = (k * ny + j) * nx + i (x fastest), two copies (A read,
 // B written) swapped every step.  Populations are stored as deviations from
-// the rest state, f - w (rho0 = 1) and g - w T_ref; 16-bit storage keeps the
-// deviation divided by w so that every direction uses the same range.
+// the rest state, f - w (rho0 = 1) and g - w T_s; 16-bit storage keeps the
+// deviation divided by w so that every direction uses the same range, with
+// T_s the middle of the case's initial temperatures (T_s = T_ref otherwise).
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -313,8 +314,10 @@ template <typename T> struct LbmArgs {
     double omf, omg;               // 1 / tau
     double gf, gg;                 // 1 - 1 / (2 tau)
     double gbeta;
-    double Tref;
-    double tw[6];                  // T_wall - T_ref per face
+    double Tref;                   // the g deviations are stored from w Tref (T_ref, or for 16-bit storage the
+                                   // middle of the case's initial temperatures)
+    double dTb;                    // Tref - T_ref: buoyancy acts on T - T_ref = (T - Tref) + dTb
+    double tw[6];                  // T_wall - Tref per face
     const void *fA, *gA;
     void *fB, *gB;
     const int *tile_start, *tile_count, *tile_items;   // items: particle patch ids
@@ -817,7 +820,7 @@ __global__ __launch_bounds__(LBM_THREADS) void k_lbm(LbmArgs<typename SF::T> a)
         const C rho = (C)1 + drho;
         const C dT = dS + (C)0.5 * QB;
         C F[3] = {FB[0], FB[1], FB[2]};
-        F[DIM - 1] += (C)a.gbeta * dT;
+        F[DIM - 1] += (C)a.gbeta * (dT + (C)a.dTb);
         // FP32 compute (16-bit storage): the hardware reciprocal (1 ulp) in
         // place of the correctly rounded division sequence
         C inv;
