@@ -81,6 +81,10 @@ def test_forward_matches_mirrored_oracle(torch_mod, pibm_mod, n):
     # decisions: a few in 10^3 relative
     assert np.linalg.norm(y - ym) <= 1e-3 * np.linalg.norm(ym)
     assert np.abs(y - ym).max() <= 1e-2 * scale
+    r = np.abs(y - ym) / scale
+    print(f"forward n={n}: elementwise |y - mirror| / max|y|: median {np.median(r):.2e}, "
+          f"share <= 1e-6 {np.mean(r <= 1e-6):.3f}, <= 1e-5 {np.mean(r <= 1e-5):.3f}, "
+          f"<= 1e-4 {np.mean(r <= 1e-4):.3f}, max {r.max():.2e}")
     # and the mirror is the right model: the exact FP64 network is further away
     assert np.linalg.norm(y - ye) > np.linalg.norm(y - ym)
     m.close()
@@ -101,6 +105,9 @@ def test_gradients_match_mirrored_oracle(torch_mod, pibm_mod):
     for k in BLOCKS:
         err = np.linalg.norm(G[k] - Gm[k]) / np.linalg.norm(Gm[k])
         assert err <= 1e-3 * 3, (k, err)
+        r = np.abs(G[k] - Gm[k]) / np.abs(Gm[k]).max()
+        print(f"grad {k}: normwise {err:.2e}; elementwise / max: median {np.median(r):.2e}, "
+              f"share <= 1e-5 {np.mean(r <= 1e-5):.3f}, <= 1e-4 {np.mean(r <= 1e-4):.3f}, max {r.max():.2e}")
     # parameters untouched
     assert np.array_equal(m.get_params(), p)
     m.close()
