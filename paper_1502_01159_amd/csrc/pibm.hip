@@ -308,7 +308,7 @@ int make_plan(const pibm_params *p, const pibm_particle *pt, int np, Plan &P)
     sz[R_TCOUNT] = (size_t)P.ntiles * sizeof(int);
     sz[R_TSTART] = (size_t)(P.ntiles + 1) * sizeof(int);
     sz[R_TFILL] = (size_t)P.ntiles * sizeof(int);
-    sz[R_TITEMS] = std::max(P.tile_cap, 1LL) * sizeof(int);
+    sz[R_TITEMS] = std::max(P.tile_cap, 1LL) * sizeof(int2);
     // a second set of tile lists: the two-stream step bins the next step into it
     sz[R_TCOUNT1] = sz[R_TCOUNT]; sz[R_TSTART1] = sz[R_TSTART]; sz[R_TFILL1] = sz[R_TFILL]; sz[R_TITEMS1] = sz[R_TITEMS];
     sz[R_CCOUNT] = (size_t)P.ncells * sizeof(int);
@@ -469,8 +469,7 @@ template <class T> LbmArgs<T> lbm_args(const pibm_ctx *c)
     a.gB = c->r(src ? R_GA : R_GB);
     a.tile_start = (const int *)c->r(c->tcur ? R_TSTART1 : R_TSTART);
     a.tile_count = (const int *)c->r(c->tcur ? R_TCOUNT1 : R_TCOUNT);
-    a.tile_items = (const int *)c->r(c->tcur ? R_TITEMS1 : R_TITEMS);
-    a.gp_start = (const int *)c->r(R_GP_START);
+    a.tile_items = (const int2 *)c->r(c->tcur ? R_TITEMS1 : R_TITEMS);
     a.mk = (const MarkerRec<T> *)c->r(R_MK);
     a.err = (int *)c->r(R_ERR);
     a.macro = nullptr;
@@ -580,11 +579,12 @@ BinArgs bin_args(pibm_ctx *c, int set)
     b.tp_start = (const int *)c->r(R_TP_START);
     b.tp_box = (const double *)c->r(R_TP_BOX);
     b.gp_base = (const int *)c->r(R_GP_BASE);
+    b.gp_start = (const int *)c->r(R_GP_START);
     b.cap = c->P.tile_cap;
     b.tile_count = (int *)c->r(set ? R_TCOUNT1 : R_TCOUNT);
     b.tile_start = (int *)c->r(set ? R_TSTART1 : R_TSTART);
     b.tile_fill = (int *)c->r(set ? R_TFILL1 : R_TFILL);
-    b.tile_items = (int *)c->r(set ? R_TITEMS1 : R_TITEMS);
+    b.tile_items = (int2 *)c->r(set ? R_TITEMS1 : R_TITEMS);
     b.err = (int *)c->r(R_ERR);
     return b;
 }

@@ -320,8 +320,8 @@ template <typename T> struct LbmArgs {
     double tw[6];                  // T_wall - Tref per face
     const void *fA, *gA;
     void *fB, *gB;
-    const int *tile_start, *tile_count, *tile_items;   // items: particle patch ids
-    const int *gp_start;           // first point of each particle patch (one more entry: the total)
+    const int *tile_start, *tile_count;
+    const int2 *tile_items;        // items: a particle patch's first point record and its point count
     const MarkerRec<T> *mk;
     int *err;
     T *macro;                      // macro pass: rho, u[3], T at k * Ns + n
@@ -600,9 +600,9 @@ __global__ __launch_bounds__(LBM_THREADS) void k_lbm(LbmArgs<typename SF::T> a)
         // while the accumulators are cleared
         int pm0 = 0, pn = 0;
         if (lane < pe - ps) {
-            const int g = a.tile_items[ps + lane];
-            pm0 = a.gp_start[g];
-            pn = a.gp_start[g + 1] - pm0;
+            const int2 it = a.tile_items[ps + lane];
+            pm0 = it.x;
+            pn = it.y;
         }
         for (int i = tid; i < NC * NROW * PXU; i += LBM_THREADS) (&acc[0][0])[i] = 0ull;
         __syncthreads();
@@ -716,9 +716,9 @@ __global__ __launch_bounds__(LBM_THREADS) void k_lbm(LbmArgs<typename SF::T> a)
             if (e0 != ps) {
                 pm0 = 0; pn = 0;
                 if (lane < ne) {
-                    const int g = a.tile_items[e0 + lane];
-                    pm0 = a.gp_start[g];
-                    pn = a.gp_start[g + 1] - pm0;
+                    const int2 it = a.tile_items[e0 + lane];
+                    pm0 = it.x;
+                    pn = it.y;
                 }
             }
             int incl = pn;                            // inclusive prefix over the batch
@@ -1605,8 +1605,10 @@ struct BinArgs {
     const int *tp_start;           // ntmpl + 1: first patch of each template
     const double *tp_box;          // 6 per patch: least and greatest offset per axis
     const int *gp_base;            // np + 1: first patch id of each particle
+    const int *gp_start;           // first point record of each patch (one more entry: the total)
     long long cap;                 // capacity of tile_items
-    int *tile_count, *tile_start, *tile_fill, *tile_items;
+    int *tile_count, *tile_start, *tile_fill;
+    int2 *tile_items;              // (first point record, point count) of each listed patch
     int *err;
 };
 
@@ -1704,7 +1706,12 @@ __device__ __forceinline__ void bin_particle(const BinArgs &a, int p, int lane)
             if (FILL) {
                 const int pos = atomicAdd(&a.tile_fill[t], 1);
                 const long long at = (long long)a.tile_start[t] + pos;
-                if (at < a.cap) a.tile_items[at] = g0 + kb + e;
+                if (at < a.cap) {
+                    // the patch's range of point records, so that the lattice kernel
+                    // reads it with the list instead of one dependent load later
+                    const int g = g0 + kb + e;
+                    a.tile_items[at] = make_int2(a.gp_start[g], a.gp_start[g + 1] - a.gp_start[g]);
+                }
                 else atomicOr(a.err, ERR_TILES);
             } else {
                 atomicAdd(&a.tile_count[t], 1);

@@ -80,11 +80,17 @@ def test_forward_matches_mirrored_oracle(torch_mod, pibm_mod, n):
     # FP32 accumulation order and the FP32 GELU only move BF16 rounding
     # decisions: a few in 10^3 relative
     assert np.linalg.norm(y - ym) <= 1e-3 * np.linalg.norm(ym)
-    assert np.abs(y - ym).max() <= 1e-2 * scale
+    # Element by element: an output whose BF16 activations all round as in the
+    # mirror differs only by the FP32 accumulation order (measured <= 1e-7 of
+    # the largest output); one activation rounded to the other BF16 neighbour
+    # moves it by up to its weight times 2^-8 of the activation (measured max
+    # 1.2e-3, in 2% of the outputs of 1000 samples, none of 1 or 37).
     r = np.abs(y - ym) / scale
     print(f"forward n={n}: elementwise |y - mirror| / max|y|: median {np.median(r):.2e}, "
           f"share <= 1e-6 {np.mean(r <= 1e-6):.3f}, <= 1e-5 {np.mean(r <= 1e-5):.3f}, "
           f"<= 1e-4 {np.mean(r <= 1e-4):.3f}, max {r.max():.2e}")
+    assert np.mean(r <= 1e-6) >= 0.95
+    assert r.max() <= 3e-3
     # and the mirror is the right model: the exact FP64 network is further away
     assert np.linalg.norm(y - ye) > np.linalg.norm(y - ym)
     m.close()
@@ -105,9 +111,11 @@ def test_gradients_match_mirrored_oracle(torch_mod, pibm_mod):
     for k in BLOCKS:
         err = np.linalg.norm(G[k] - Gm[k]) / np.linalg.norm(Gm[k])
         assert err <= 1e-3 * 3, (k, err)
+        # element by element against the block's largest gradient (measured max 4.4e-4)
         r = np.abs(G[k] - Gm[k]) / np.abs(Gm[k]).max()
         print(f"grad {k}: normwise {err:.2e}; elementwise / max: median {np.median(r):.2e}, "
               f"share <= 1e-5 {np.mean(r <= 1e-5):.3f}, <= 1e-4 {np.mean(r <= 1e-4):.3f}, max {r.max():.2e}")
+        assert r.max() <= 1e-3, (k, r.max())
     # parameters untouched
     assert np.array_equal(m.get_params(), p)
     m.close()
