@@ -420,7 +420,7 @@ __device__ __forceinline__ void pull(const LbmArgs<T> &a, int x, int y, int z, T
     }
 }
 
-// Raw moments of the streamed deviations: rho - 1, j, S - T_ref.
+// Raw moments of the streamed deviations: rho - 1, j, S - T_s (T_s: the g storage offset, Tref).
 template <int DIM, class L, class C, class T>
 __device__ __forceinline__ void moments(const T *f, const C *g, C &drho, C *j, C &dS)
 {
@@ -797,7 +797,7 @@ __global__ __launch_bounds__(LBM_THREADS) void k_lbm(LbmArgs<typename SF::T> a)
         C fc[L::Q];
 #pragma unroll
         for (int q = 0; q < L::Q; ++q) fc[q] = (C)f[q];
-        // raw moments rho - 1, j, S - T_ref, summed over opposite pairs
+        // raw moments rho - 1, j, S - Tref, summed over opposite pairs
         C drho = (C)(SC ? L::w(0) : 1.0) * fc[0], j[3] = {0, 0, 0};
 #pragma unroll
         for (int q = 1; q < L::Q; ++q) {
@@ -999,7 +999,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k
     __shared__ uint32_t bits[K2_MAXBOX / 32];
     __shared__ int woff[K2_MAXBOX / 32 + 1];
     __shared__ int cell[MAXSHELL];
-    __shared__ T mom[DIM + 2][MAXSHELL];          // rho - 1, j, S - T_ref per stencil node
+    __shared__ T mom[DIM + 2][MAXSHELL];          // rho - 1, j, S - Tref per stencil node
     __shared__ int s_total;
     // Particles in cell-list order, in runs of consecutive ones per XCD (as
     // the lattice tiles): neighbours' stencil rows share 128-byte lines, which
@@ -1300,7 +1300,7 @@ __global__ __launch_bounds__(FEAT_THREADS) void k_features(FeatArgs<typename SF:
     for (int d = 0; d < DIM; ++d) sane = sane && ext[d] >= 1 && ext[d] <= 4096;
     const int nbox = sane ? ext[0] * ext[1] * ext[2] : 0;   // non-finite centre: empty shell
     if (wv < MW) {
-        double sm[5] = {0, 0, 0, 0, 0};               // rho, j, S - T_ref
+        double sm[5] = {0, 0, 0, 0, 0};               // rho, j, S - Tref
         double cnt = 0.0;
         for (int o = tid; o < nbox; o += 64 * MW) {
             int c[3] = {0, 0, 0};
@@ -2155,7 +2155,7 @@ __global__ __launch_bounds__(DEM_ONE_WG) void k_dem_one_wg(DemOneWg f)
 
 
 // Initial state: f = w rho0 and g = w T_init, i.e. deviations 0 and
-// w (T_init - T_ref).
+// w (T_init - T_s) (dTinit), T_s the temperature the g deviations are stored from.
 template <class SF, class L>
 __global__ void k_init(void *f, void *g, long long N, long long Ns, typename SF::T dTinit)
 {
