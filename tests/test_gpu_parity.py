@@ -316,6 +316,30 @@ def test_checkpoint_roundtrip(gpu):
     assert np.array_equal(f1, f2) and np.array_equal(g1, g2) and np.array_equal(q1, q2)
 
 
+def test_checkpoint_restores_16bit_storage_offset(gpu):
+    """16-bit storage keeps g's deviation from an offset set by the case's
+    initial temperatures.  A checkpoint carries it: a context set up with
+    other particle temperatures (hence another offset) that loads the blob
+    holds the same populations and continues the run bit for bit."""
+    cfg, P = W.workload("c2_small")
+    a = gpu.Simulation(cfg, P, storage="f16")
+    a.step(20)
+    blob = a.save()
+    P2 = np.array(P, dtype=float)
+    P2[:, 11] = 3.0                                  # particle temperatures: another offset
+    b = gpu.Simulation(cfg, P2, storage="f16")
+    b.load(blob)
+    fa, ga = a.populations()
+    fb, gb = b.populations()
+    assert np.array_equal(fa, fb) and np.array_equal(ga, gb)
+    a.step(10)
+    b.step(10)
+    for x, y in zip(a.populations() + a.particles(), b.populations() + b.particles()):
+        assert np.array_equal(x, y)
+    a.close()
+    b.close()
+
+
 def test_watchdog_reports_runaway_velocity(gpu):
     """A node driven past |u| = 0.4 (finite values, set from the host) trips
     the device watchdog: PIBM_EUNSTABLE, later steps are refused and the
