@@ -170,8 +170,10 @@ __device__ __forceinline__ uint32_t sr_bits(uint32_t seed, int k)
 // in the next step, and keeping it out of L2 leaves room there for the
 // neighbouring tiles' rows that this step's gathers read again.
 // --------------------------------------------------------------------------
+struct SpreadF48; struct SpreadF32; struct SpreadD64;
 struct StF32 {
     using S = float; using T = float; using C = double;
+    using Spread = SpreadF48;
     static constexpr bool SCALED = false;     // stored deviation is f - w (not divided by w)
     static __device__ __forceinline__ T cvt(S v, double) { return v; }
     static __device__ __forceinline__ void st(S *p, T v, double) { *p = v; }
@@ -186,6 +188,7 @@ struct StF32 {
 };
 struct StF64 {
     using S = double; using T = double; using C = double;
+    using Spread = SpreadD64;
     static constexpr bool SCALED = false;
     static __device__ __forceinline__ T cvt(S v, double) { return v; }
     static __device__ __forceinline__ void st(S *p, T v, double) { *p = v; }
@@ -198,6 +201,7 @@ typedef __attribute__((ext_vector_type(2))) _Float16 h2x;   // the conversions' 
 typedef __attribute__((ext_vector_type(2))) __bf16 bf2x;
 struct StF16 {
     using S = __half; using T = float; using C = float;
+    using Spread = SpreadF48;
     static constexpr bool SCALED = true;      // stored deviation is (f - w) / w
     static __device__ __forceinline__ T cvt(S v, double w) { return __half2float(v) * (float)w; }
     static __device__ __forceinline__ void st(S *p, T v, double w) { *p = __float2half_rn(v * (float)(1.0 / w)); }
@@ -213,6 +217,7 @@ struct StF16 {
 };
 struct StBF16 {
     using S = uint16_t; using T = float; using C = float;
+    using Spread = SpreadF32;
     static constexpr bool SCALED = true;
     static __device__ __forceinline__ T cvt(S v, double w) { return __uint_as_float(((uint32_t)v) << 16) * (float)w; }
     static __device__ __forceinline__ void st(S *p, T v, double w)
@@ -476,43 +481,57 @@ __device__ __forceinline__ int wrap_or_out(int c, int n, int per)
 // sum appends one (point, row) entry per such row to the wave's LDS queue;
 // (3) whenever 64 entries are queued, each lane takes one and adds the
 // row's four nodes into the tile's accumulators.  The accumulators are
-// 64-bit fixed point (see SpreadFix): integer addition does not depend on order,
+// integer fixed point (the Spread formats below): integer addition does not depend on order,
 // so the result is the same bit for bit whatever the interleaving of lanes,
 // waves and list entries, with no atomics on floating point.
 // --------------------------------------------------------------------------
-// Fixed-point format of the spreading accumulators per point-record type.
+// Fixed-point format of the spreading accumulators, per storage format.
 // A contribution is a component v of a point record (clamped to |v| <= LIM,
 // which also maps NaN to a finite value that the node's velocity check then
 // flags) times the SCALE and one kernel weight w per axis.
-// FP32 records (FP32 / 16-bit storage): resolution 2^-36.  term() forms
-// v w + 1.5 2^52 in one FP64 FMA; the product of the two floats is exact, and
-// the sum's low 48 bits hold round(v w) in two's complement on top of the
-// shifter's bits, which lie above bit 47.  The accumulator adds these words
-// unchanged: the shifters pile up above bit 47 only, so the low 48 bits,
-// sign-extended once per node, are the exact sum while it stays below 2^47
-// (|F_B|, |Q_B| < 2048 at a node; a maximal contribution is 2^41, and any
-// state the watchdog lets run is orders of magnitude below).
-// FP64 records (the parity path): resolution 2^-50, |v| <= 64, exact
-// round-to-nearest conversion, int64 sums.
-template <class T> struct SpreadFix;
-template <> struct SpreadFix<float> {
+// FP32 storage (FP32 records): resolution 2^-36.  term() forms v w + 1.5 2^52
+// in one FP64 FMA; the product of the two floats is exact, and the sum's low
+// 48 bits hold round(v w) in two's complement on top of the shifter's bits,
+// which lie above bit 47.  The accumulator adds these words unchanged: the
+// shifters pile up above bit 47 only, so the low 48 bits, sign-extended once
+// per node, are the exact sum while it stays below 2^47 (|F_B|, |Q_B| < 2048
+// at a node; a maximal contribution is 2^41, and any state the watchdog lets
+// run is orders of magnitude below).
+// BF16 storage (FP32 records): 32-bit accumulators at 2^-24, from the low
+// 32 bits of the same FMA; exact while |F_B|, |Q_B| < 128 at a node (a
+// maximal contribution, |v| = 32, is 2^26).  They halve the tile's LDS (22.8
+// instead of 39.4 KB), so that a fifth workgroup fits on a CU.  A typical
+// contribution (a point force near 1e-4 times a kernel weight of a few
+// hundredths) is a few tens of units, so each is rounded by a percent or
+// more: still below what BF16's own rounding (2^-9) puts in the fields; FP16
+// storage keeps the 48-bit format, since at this resolution its velocity
+// error grew threefold.
+
+// FP64 storage (FP64 records, the parity path): resolution 2^-50, |v| <= 64,
+// exact round-to-nearest conversion, int64 sums.
+struct SpreadF48 {
+    using A = unsigned long long;
     static constexpr float SCALE = 0x1p36f, LIM = 256.0f;
-    static __device__ __forceinline__ unsigned long long term(double v, double w)
+    static __device__ __forceinline__ A term(double v, double w)
     {
-        return (unsigned long long)__double_as_longlong(fma(v, w, 0x1.8p52));
+        return (A)__double_as_longlong(fma(v, w, 0x1.8p52));
     }
-    static __device__ __forceinline__ double value(unsigned long long a)
-    {
-        return (double)((long long)(a << 16) >> 16) * 0x1p-36;
-    }
+    static __device__ __forceinline__ double value(A a) { return (double)((long long)(a << 16) >> 16) * 0x1p-36; }
 };
-template <> struct SpreadFix<double> {
-    static constexpr double SCALE = 0x1p50, LIM = 64.0;
-    static __device__ __forceinline__ unsigned long long term(double v, double w)
+struct SpreadF32 {
+    using A = unsigned int;
+    static constexpr float SCALE = 0x1p24f, LIM = 32.0f;
+    static __device__ __forceinline__ A term(double v, double w)
     {
-        return (unsigned long long)(long long)rint(v * w);
+        return (A)(unsigned long long)__double_as_longlong(fma(v, w, 0x1.8p52));
     }
-    static __device__ __forceinline__ double value(unsigned long long a) { return (double)(long long)a * 0x1p-50; }
+    static __device__ __forceinline__ double value(A a) { return (double)(int)a * 0x1p-24; }
+};
+struct SpreadD64 {
+    using A = unsigned long long;
+    static constexpr double SCALE = 0x1p50, LIM = 64.0;
+    static __device__ __forceinline__ A term(double v, double w) { return (A)(long long)rint(v * w); }
+    static __device__ __forceinline__ double value(A a) { return (double)(long long)a * 0x1p-50; }
 };
 
 // Node index on one axis: wrapped on periodic axes, unchanged otherwise (a
@@ -579,7 +598,8 @@ __global__ __launch_bounds__(LBM_THREADS) void k_lbm(LbmArgs<typename SF::T> a)
     // words so that the rows of one point's footprint, queued on adjacent
     // lanes, fall on different LDS banks
     constexpr int PXU = TL::X + 1, NROW = TL::Y * TL::Z;
-    __shared__ unsigned long long acc[NC][NROW * PXU];
+    using SP = typename SF::Spread;
+    __shared__ typename SP::A acc[NC][NROW * PXU];
     __shared__ int queue[LBM_THREADS / 64][QCAP];
 
     // XCD-aware order: consecutive workgroups go to different XCDs (round
@@ -604,7 +624,7 @@ __global__ __launch_bounds__(LBM_THREADS) void k_lbm(LbmArgs<typename SF::T> a)
             pm0 = it.x;
             pn = it.y;
         }
-        for (int i = tid; i < NC * NROW * PXU; i += LBM_THREADS) (&acc[0][0])[i] = 0ull;
+        for (int i = tid; i < NC * NROW * PXU; i += LBM_THREADS) (&acc[0][0])[i] = 0;
         __syncthreads();
         int *q = queue[wv];
         int qn = 0;                                   // wave-uniform queue length
@@ -642,8 +662,8 @@ __global__ __launch_bounds__(LBM_THREADS) void k_lbm(LbmArgs<typename SF::T> a)
             double v[NC];
 #pragma unroll
             for (int c = 0; c < NC; ++c) {
-                const T cl = fmin(fmax(r.f[c], -SpreadFix<T>::LIM), SpreadFix<T>::LIM);   // NaN -> -limit
-                v[c] = (double)(cl * SpreadFix<T>::SCALE * wyz);
+                const T cl = fmin(fmax(r.f[c], (T)-SP::LIM), (T)SP::LIM);   // NaN -> -limit
+                v[c] = (double)(cl * (T)SP::SCALE * wyz);
             }
 #pragma unroll
             for (int kx = 0; kx < 4; ++kx) {
@@ -651,7 +671,7 @@ __global__ __launch_bounds__(LBM_THREADS) void k_lbm(LbmArgs<typename SF::T> a)
                 if (lx >= 0 && lx < TL::X) {
                     const double wx = (double)w0[kx];
 #pragma unroll
-                    for (int c = 0; c < NC; ++c) atomicAdd(&acc[c][row + lx], SpreadFix<T>::term(v[c], wx));
+                    for (int c = 0; c < NC; ++c) atomicAdd(&acc[c][row + lx], SP::term(v[c], wx));
                 }
             }
         };
@@ -779,7 +799,7 @@ __global__ __launch_bounds__(LBM_THREADS) void k_lbm(LbmArgs<typename SF::T> a)
         if (has) {
 #pragma unroll
             for (int c = 0; c < NC; ++c) {
-                const C v = (C)SpreadFix<T>::value(acc[c][lr * PXU + lx]);
+                const C v = (C)SP::value(acc[c][lr * PXU + lx]);
                 if (c < DIM) FB[c] = v;
                 else QB = v;
             }
