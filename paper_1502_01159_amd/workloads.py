@@ -138,15 +138,23 @@ def sediment_3d(nx: int = 256, ny: int = 256, nz: int = 512, n_spheres: int = 20
     return cfg, P
 
 
-def thermo_3d(n: int = 384, n_spheres: int = 20000, D: float = 10.0, seed: int = 4, Gr: float = 100.0):
+def thermo_3d(n: int = 384, n_spheres: int = 20000, D: float = 10.0, seed: int = 4, Gr: float = 100.0,
+              rho_r: float = 1.25):
     """3D thermosensitive spheres (Sec. 3.4 stand-in): a jittered lattice of
     sites filling the upper part of the box, a seeded subset of them kept,
-    initial particle temperature uniform in [0, 1)."""
+    initial particle temperature uniform in [0, 1).
+
+    Density ratio 1.25 (the case leaves it open).  At 1.05, as for the heated
+    spheres of the sedimentation case, the explicit point exchange amplifies
+    the spin of these D = 10 spheres, whose layers start 1 lu apart, by about
+    6% a step, and runs diverge within 250 steps; at 1.15 and 1.25 they run
+    the case's 5000 steps.  Gravity is scaled so that (rho_r - 1) g, which
+    sets the settling speed, stays that of the sedimentation case."""
     cfg = dict(
         name=f"thermo3d_{n}_{n_spheres}", dim=3, nx=n, ny=n, nz=n, periodic=[0, 0, 0],
         T_wall=[0.0] * 6, T_init=0.5, T_ref=0.5,
         Ra=0.0, nu=0.025, Pr=0.7, Gr=Gr, Lc=D,
-        gravity=4.167e-3, kappa_T=1.0, marker_mode=1, marker_spacing=1.0,
+        gravity=4.167e-3 * 0.05 / (rho_r - 1.0), kappa_T=1.0, marker_mode=1, marker_spacing=1.0,
         E_star=729.0, poisson=0.33, mu_fric=0.3, n_sub=11, beta_p=0.05, c_r=1.0,
     )
     R = 0.5 * D
@@ -176,7 +184,7 @@ def thermo_3d(n: int = 384, n_spheres: int = 20000, D: float = 10.0, seed: int =
     P = []
     for s in keep:
         x = sites[s] + (np.array([rng.uniform(), rng.uniform(), rng.uniform()]) - 0.5)
-        P.append(_row(x, R, 1.05, rng.uniform(), THERMO))
+        P.append(_row(x, R, rho_r, rng.uniform(), THERMO))
     return cfg, np.array(P)
 
 
@@ -270,7 +278,8 @@ def workload(name: str):
     """Named workloads.  Full sizes:
     c1 annulus 64^2; c2 2D sedimentation 512x1024, 100 disks; c3 3D
     sedimentation 256x256x512, 2000 spheres; c4 thermosensitive 384^3, 20000
-    spheres; x3 / x3_noheat the paper's planted 15^3 case with 8125 point
+    spheres (c3_mid and c4_mid: the same with a box 4 times smaller per
+    axis); x3 / x3_noheat the paper's planted 15^3 case with 8125 point
     particles, with and without thermal buoyancy; packed_bed 107 spheres in
     contact on a floor.  Small variants (suffix _small) keep the structure for parity
     runs that the oracle finishes in seconds."""
@@ -296,6 +305,11 @@ def workload(name: str):
         return thermo_3d()
     if name == "c4_small":
         return thermo_3d(n=48, n_spheres=9, D=10.0, seed=14)
+    if name == "c4_mid":
+        # the 384^3 case with a box 4 times smaller per axis: 6 layers of
+        # 7 x 7 sites over the upper three quarters of the height, 288 of the
+        # 294 kept (the full case keeps 20000 of 26 x 28 x 28)
+        return thermo_3d(n=96, n_spheres=288, D=10.0, seed=16)
     if name == "x3":
         return planted_3d(heat=True)
     if name == "x3_noheat":

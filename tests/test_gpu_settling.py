@@ -47,3 +47,30 @@ def test_buoyancy_delays_settling(gpu):
     # the second half is under a fifth of the isothermal one
     w = {gr: np.mean(rows[len(rows) // 2:, 3]) for gr, rows in h.items()}
     assert w[0] < 0 and abs(w[1000]) < 0.2 * abs(w[0])
+
+
+@pytest.mark.parametrize("name", ["c4_mid", "c4"])
+def test_thermosensitive_case_runs_its_5000_steps(gpu, name):
+    """The thermosensitive case over the 5000 steps it is specified for
+    (FP32, the benchmark's launch configuration): the device watchdog stays
+    silent while the spheres settle onto the floor, spins stay small, and the
+    particle temperatures stay within the range of the initial ones and the
+    walls.  At a density ratio of 1.05 the explicit point exchange amplifies
+    these spheres' spin and the watchdog stops the run within 500 steps; the
+    case takes 1.25."""
+    cfg, P = W.workload(name)
+    sim = gpu.Simulation(cfg, P, storage="f32")
+    low0 = float((P[:, 2] - P[:, 9]).min())
+    for k in range(10):
+        sim.step(500)
+        assert sim.sync() == gpu.OK, f"watchdog before step {(k + 1) * 500}"
+    q, _ = sim.particles()
+    low, om = float((q[:, 2] - q[:, 12]).min()), float(np.abs(q[:, 6:9]).max())
+    print(f"{name}: lowest bottom {low0:.1f} -> {low:.1f}, max |Omega| {om:.2e}, T_p in [{q[:, 14].min():.3f}, "
+          f"{q[:, 14].max():.3f}]", flush=True)
+    # measured: the lowest sphere rests on the floor (bottom at the halfway
+    # wall, -0.5) in both; max |Omega| 2.2e-3 (c4_mid) and 2.8e-3 (c4)
+    assert low < 1.0 and low0 > 20.0
+    assert om < 0.02
+    assert q[:, 14].min() >= 0.0 and q[:, 14].max() <= 1.0
+    sim.close()

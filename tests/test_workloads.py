@@ -27,7 +27,7 @@ def _check(cfg, P):
         assert np.linalg.norm(X[i] - X[j]) >= R[i] + R[j] - 1e-9
 
 
-@pytest.mark.parametrize("name", ["c1", "c2", "c2_small", "c3_small", "c4_small", "c3", "c4"])
+@pytest.mark.parametrize("name", ["c1", "c2", "c2_small", "c3_small", "c3_mid", "c4_small", "c4_mid", "c3", "c4"])
 def test_workloads_valid_and_reproducible(name):
     cfg, P = W.workload(name)
     _check(cfg, P)
@@ -41,6 +41,9 @@ def test_full_sizes():
     assert np.all(P[:, 9] == 6.0) and np.all(P[:, 10] == 1.05)
     cfg, P = W.workload("c4")
     assert (cfg["nx"], len(P)) == (384, 20000)
+    # density ratio 1.25, with (rho_r - 1) g that of the heated spheres above
+    assert np.all(P[:, 10] == 1.25)
+    assert abs((1.25 - 1.0) * cfg["gravity"] - 0.05 * W.workload("c3")[0]["gravity"]) < 1e-12
     assert np.all(P[:, 12] == W.THERMO)
     assert 0.0 <= P[:, 11].min() and P[:, 11].max() < 1.0
     cfg, P = W.workload("c2")
