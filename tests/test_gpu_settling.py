@@ -74,3 +74,25 @@ def test_thermosensitive_case_runs_its_5000_steps(gpu, name):
     assert om < 0.02
     assert q[:, 14].min() >= 0.0 and q[:, 14].max() <= 1.0
     sim.close()
+
+
+@pytest.mark.parametrize("name,steps", [("c2", 20000), ("c3", 5000)])
+def test_sedimentation_cases_run_their_specified_steps(gpu, name, steps):
+    """The 2D and 3D sedimentation of hot particles over the steps they are
+    specified for (FP32, the benchmark's launch configuration): the device
+    watchdog stays silent, the cloud settles, spins stay small."""
+    cfg, P = W.workload(name)
+    up = cfg["dim"] - 1
+    sim = gpu.Simulation(cfg, P, storage="f32")
+    chunk = steps // 10
+    for k in range(10):
+        sim.step(chunk)
+        assert sim.sync() == gpu.OK, f"watchdog before step {(k + 1) * chunk}"
+    q, _ = sim.particles()
+    fall, om = float(P[:, up].mean() - q[:, up].mean()), float(np.abs(q[:, 6:9]).max())
+    print(f"{name} {steps} steps: mean height fell by {fall:.1f}, max |Omega| {om:.2e}", flush=True)
+    # measured: the mean height fell by 61.1 (c2) and 42.7 (c3); max |Omega|
+    # 1.9e-3 and 1.3e-3
+    assert fall > 10.0
+    assert om < 0.02
+    sim.close()
