@@ -30,7 +30,7 @@ METRIC = "MLUPS (coupled flow+thermal+PIBM), % HBM roofline; FP32 vs FP16-storag
 WORKLOAD_TEXT = {
     "c2": "2D sedimentation of hot disks: D2Q9+D2Q5, 512x1024, 100 disks D=20, Gr=500",
     "c3": "3D sedimentation of heated spheres: D3Q19+D3Q7, 256x256x512, 2000 spheres D=12, Gr=100",
-    "c4": "3D thermosensitive spheres: D3Q19+D3Q7, 384^3, 20000 spheres D=10, Gr=100",
+    "c4": "3D thermosensitive spheres: D3Q19+D3Q7, 384^3, 20000 spheres D=10, density ratio 1.25, Gr=100",
 }
 STORAGE_BYTES = {"f32": 4, "f64": 8, "f16": 2, "bf16": 2}
 # storage type of the populations and the type the collision computes in
