@@ -596,6 +596,10 @@ int launch_bin(pibm_ctx *c, hipStream_t s, int set)
     BinArgs b = bin_args(c, set);
     const int nt = c->P.ntiles;
     int *cntr = (int *)c->r(R_CNTR);
+    if (c->P.np <= BIN_ONE_WG_PARTICLES && nt <= BIN_ONE_WG_TILES) {   // few particles and tiles: one launch
+        hipLaunchKernelGGL(k_bin_one_wg, dim3(1), dim3(1024), 0, s, b, nt, cntr);
+        return hip_ok(c, hipGetLastError());
+    }
     hipLaunchKernelGGL(k_zero2, dim3(std::min(1024, (nt + 256) / 256)), dim3(256), 0, s, b.tile_count, (long long)nt,
                        cntr, 1LL);
     const int gb = (c->P.np + BIN_THREADS / 64 - 1) / (BIN_THREADS / 64);

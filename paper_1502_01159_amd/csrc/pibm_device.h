@@ -1747,6 +1747,78 @@ __global__ __launch_bounds__(BIN_THREADS) void k_bin(BinArgs a)
     if (p < a.np) bin_particle<FILL>(a, p, lane);
 }
 
+// One thread per patch: global patch g (patch g - base[p] of particle p's
+// template, base = the particles' first patch ids, np + 1 entries) counted
+// into or listed in the tiles its points' footprints can reach, as in
+// bin_particle.  The ranges are read with atomic loads: they were written by
+// other waves of the same workgroup in this launch.
+constexpr int BIN_ONE_WG_PARTICLES = 256, BIN_ONE_WG_TILES = 16384;
+template <bool FILL>
+__device__ __forceinline__ void bin_patch(const BinArgs &a, int g, const int *base)
+{
+    int p = 0;                                     // the last particle with base[p] <= g
+#pragma unroll
+    for (int st = BIN_ONE_WG_PARTICLES / 2; st; st >>= 1)
+        if (p + st < a.np && base[p + st] <= g) p += st;
+    const DevParticle P = a.part[p];
+    const int k = g - base[p];
+    if (!centre_ok(P, a.dim)) {
+        if (!FILL && k == 0) atomicOr(a.err, ERR_DOMAIN);
+        return;
+    }
+    const double *bx = a.tp_box + 6 * (size_t)(a.tp_start[P.tmpl] + k);
+    const int nn[3] = {a.nx, a.ny, a.nz}, TT[3] = {a.TX, a.TY, a.TZ};
+    AxisRun r[3] = {{0, 1, 1}, {0, 1, 1}, {0, 1, 1}};
+#pragma unroll
+    for (int d = 0; d < 3; ++d)
+        if (d < a.dim)
+            r[d] = axis_run((int)floor(P.x[d] + bx[d]) - 1, (int)floor(P.x[d] + bx[3 + d]) + 2, nn[d], a.per[d], TT[d]);
+    const int ncomb = r[0].cnt * r[1].cnt * r[2].cnt;
+    int2 item = make_int2(0, 0);
+    if (FILL) item = make_int2(a.gp_start[g], a.gp_start[g + 1] - a.gp_start[g]);
+    for (int c = 0; c < ncomb; ++c) {
+        const int ix = c % r[0].cnt, iy = (c / r[0].cnt) % r[1].cnt, iz = c / (r[0].cnt * r[1].cnt);
+        const int t = (axis_tile(r[2], iz) * a.nty + axis_tile(r[1], iy)) * a.ntx + axis_tile(r[0], ix);
+        if (FILL) {
+            const int pos = atomicAdd(&a.tile_fill[t], 1);
+            const long long at = (long long)__atomic_load_n(&a.tile_start[t], __ATOMIC_RELAXED) + pos;
+            if (at < a.cap) a.tile_items[at] = item;
+            else atomicOr(a.err, ERR_TILES);
+        } else {
+            atomicAdd(&a.tile_count[t], 1);
+        }
+    }
+}
+
+__device__ __forceinline__ void alloc_one_wg(const int *count, int *start, int *fill, int n, int *total);
+
+// Few particles and tiles: the four phases of binning (zero, count, ranges,
+// fill: k_zero2, k_bin, k_alloc, k_bin) in one workgroup of ONE_WG threads,
+// one thread per patch, barriers between the phases.  Before each barrier a
+// wave waits until its global stores and atomics are done, so that the next
+// phase's atomics and loads in other waves find them.  The lists hold the
+// same items as k_bin's, in another order within a tile, which no result
+// depends on.
+__global__ __launch_bounds__(1024) void k_bin_one_wg(BinArgs a, int nt, int *total)
+{
+    __shared__ int base[BIN_ONE_WG_PARTICLES + 1];
+    const int tid = threadIdx.x;
+    if (block_halted(a.err)) return;
+    for (int i = tid; i < nt; i += 1024) a.tile_count[i] = 0;
+    if (tid == 0) *total = 0;
+    for (int p = tid; p <= a.np; p += 1024) base[p] = a.gp_base[p];
+    __builtin_amdgcn_s_waitcnt(0);
+    __syncthreads();
+    const int npatch = base[a.np];
+    for (int g = tid; g < npatch; g += 1024) bin_patch<false>(a, g, base);
+    __builtin_amdgcn_s_waitcnt(0);
+    __syncthreads();
+    alloc_one_wg(a.tile_count, a.tile_start, a.tile_fill, nt, total);
+    __builtin_amdgcn_s_waitcnt(0);
+    __syncthreads();
+    for (int g = tid; g < npatch; g += 1024) bin_patch<true>(a, g, base);
+}
+
 __global__ void k_fill_int(int *p, long long n, int v)
 {
     for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x)
