@@ -696,7 +696,8 @@ int launch_dem(pibm_ctx *c, hipStream_t s)
         f.hn[1] = (int *)c->r(c->hcur ? R_HN0 : R_HN1);
         f.n_sub = c->p.n_sub;
         const int threads = (c->P.np + 63) / 64 * 64;
-        hipLaunchKernelGGL(k_dem_one_wg, dim3(1), dim3(threads), 0, s, f);
+        if (c->P.np <= DEM_LDS) hipLaunchKernelGGL(k_dem_one_wg_lds, dim3(1), dim3(threads), 0, s, f);
+        else hipLaunchKernelGGL(k_dem_one_wg, dim3(1), dim3(threads), 0, s, f);
         if (c->p.n_sub & 1) { c->pcur ^= 1; c->hcur ^= 1; }
         c->cells_ok = 0;
         return hip_ok(c, hipGetLastError());

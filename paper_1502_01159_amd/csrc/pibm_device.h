@@ -2245,6 +2245,36 @@ __global__ __launch_bounds__(DEM_ONE_WG) void k_dem_one_wg(DemOneWg f)
     }
 }
 
+// Up to DEM_LDS particles: as k_dem_one_wg, with the particle state kept in
+// LDS through the sub-steps (two copies in place of the two global buffers),
+// so that a sub-step reads its own and its neighbours' states without a
+// round trip to L2.  Both copies go back to the global buffers at the end:
+// these then hold what the sub-steps one launch each would leave.
+constexpr int DEM_LDS = 256;
+__global__ __launch_bounds__(DEM_LDS) void k_dem_one_wg_lds(DemOneWg f)
+{
+    __shared__ DevParticle buf[2][DEM_LDS];
+    const int i = threadIdx.x;
+    const bool mine = i < f.a.np;
+    if (mine) buf[0][i] = f.part[0][i];
+    __syncthreads();
+    for (int s = 0; s < f.n_sub; ++s) {
+        DemArgs a = f.a;
+        const int c = s & 1;
+        a.cur = buf[c];
+        a.nxt = buf[c ^ 1];
+        a.hid_in = f.hid[c]; a.hxi_in = f.hxi[c]; a.hn_in = f.hn[c];
+        a.hid_out = f.hid[c ^ 1]; a.hxi_out = f.hxi[c ^ 1]; a.hn_out = f.hn[c ^ 1];
+        a.last = s == f.n_sub - 1;
+        if (mine) dem_particle(a, i);
+        __syncthreads();
+    }
+    if (mine) {
+        f.part[0][i] = buf[0][i];
+        if (f.n_sub > 0) f.part[1][i] = buf[1][i];
+    }
+}
+
 
 // Initial state: f = w rho0 and g = w T_init, i.e. deviations 0 and
 // w (T_init - T_s) (dTinit), T_s the temperature the g deviations are stored from.
