@@ -557,6 +557,26 @@ def test_point_particle_first_step_relaxation(oracle_mod, d, rho_r):
     assert abs(o.particles()[0, 3] - U0 * factor) < 1e-14
 
 
+@pytest.mark.parametrize("d,rho_r", [(4.0, 1.01), (0.25, 1.01), (1.0, 2.5)])
+def test_point_particle_first_step_relaxation_2d(oracle_mod, d, rho_r):
+    """The same in 2D, where a point particle's weight is its cross-section
+    per unit depth, A_p = d, and its mass rho_r pi d^2 / 4 (unit depth): the
+    reaction is -2 A_p U0 and one step gives U0 (1 - 8 / (pi rho_r d)).  For
+    the sub-grid particles of the paper's 2D case (d = h / 4, rho_r = 1.01)
+    the factor is -9.09."""
+    U0 = 0.01
+    cfg = base2d(nx=12, ny=12, marker_mode=2)
+    P = np.array([prow((5.5, 5.5, 0.0), 0.5 * d, rho_r=rho_r, u=(U0, 0.0, 0.0))])
+    o = oracle_mod.Oracle(cfg, P)
+    o.step(1)
+    r = o.reactions()[0]
+    assert abs(r[0] + 2.0 * d * U0) < 1e-15 and np.abs(r[1:6]).max() < 1e-15
+    factor = 1.0 - 8.0 / (math.pi * rho_r * d)
+    assert abs(o.particles()[0, 3] - U0 * factor) < 1e-14
+    if d == 0.25:
+        assert factor == pytest.approx(-9.085, abs=1e-3)
+
+
 # --------------------------------------------------------------------------- #
 # Symmetry (P10)                                                               #
 # --------------------------------------------------------------------------- #

@@ -27,7 +27,7 @@ def _check(cfg, P):
         assert np.linalg.norm(X[i] - X[j]) >= R[i] + R[j] - 1e-9
 
 
-@pytest.mark.parametrize("name", ["c1", "c2", "c2_small", "c3_small", "c3_mid", "c4_small", "c4_mid", "c3", "c4"])
+@pytest.mark.parametrize("name", ["c1", "c2", "c2_small", "c3_small", "c3_mid", "c4_small", "c4_mid", "c3", "c4", "x2"])
 def test_workloads_valid_and_reproducible(name):
     cfg, P = W.workload(name)
     _check(cfg, P)
