@@ -49,6 +49,9 @@ MUTANTS = [
     ("prescribed_force_sign", "double FA[3] = {-r[0], -r[1], s->p.dim == 2 ? 0.0 : -r[2]};",
      "double FA[3] = {r[0], r[1], s->p.dim == 2 ? 0.0 : r[2]};", pins.test_prescribed_point_step_conserves_and_applies,
      dict(dim=3)),
+    # one point per sub-grid particle: its cross-section per unit depth in 2D (Sec. 2.2)
+    ("point_weight_2d", "q->area[0] = s->p.dim == 2 ? D : 0.25 * pi * D * D;", "q->area[0] = 0.25 * pi * D * D;",
+     pins.test_point_particle_first_step_relaxation_2d, dict(d=0.25, rho_r=1.01)),
     # Eqs. (lbm7)-(lbm8): the exchange factor 2
     ("exchange_factor", "Fl[d] = 2.0 * (rl * U[d] - jl[d]);", "Fl[d] = (rl * U[d] - jl[d]);",
      pins.test_interpolation_exact_for_linear_fields, dict(dim=3)),
