@@ -143,7 +143,7 @@ def workload_case(name):
 
 @pytest.mark.parametrize("name,steps", [("c1", 2000), ("c2_small", 200), ("c3_small", 60), ("c4_small", 60),
                                         ("c3_small_q15", 60), ("c1_tm1", 300), ("c3_small_q15_tm1", 60),
-                                        ("x3", 2), ("x2", 2), ("c2", 200), ("c3_mid", 200), ("c4_mid", 100)])
+                                        ("x3", 2), ("x2", 2), ("x2_noheat", 2), ("c2", 200), ("c3_mid", 200), ("c4_mid", 100)])
 def test_workloads_f64(gpu, oracle_mod, name, steps):
     cfg, P = workload_case(name)
     sim, ref = run_pair(gpu, oracle_mod, cfg, P, steps, "f64")
