@@ -674,6 +674,26 @@ int build_cells(pibm_ctx *c, hipStream_t s)
     return hip_ok(c, hipGetLastError());
 }
 
+// Few particles, cells and tiles: the cell list and the tile lists (set
+// `set`) of the current particle state in one launch.  Binning reads only
+// the particle state, so on one stream it can precede the exchange.
+bool cells_bin_fused(const pibm_ctx *c)
+{
+    return c->P.np > 0 && !c->cells_ok && c->P.np <= ONE_WG_PARTICLES && c->P.ncells <= ONE_WG_LISTS &&
+           c->P.np <= BIN_ONE_WG_PARTICLES && c->P.ntiles <= BIN_ONE_WG_TILES;
+}
+int launch_cells_bin(pibm_ctx *c, hipStream_t s, int set)
+{
+    DemArgs a = dem_args(c);
+    a.cur = (const DevParticle *)c->r(c->pcur ? R_PART1 : R_PART0);
+    const BinArgs b = bin_args(c, set);
+    int *cntr = (int *)c->r(R_CNTR);
+    hipLaunchKernelGGL(k_cells_bin_one_wg, dim3(1), dim3(ONE_WG), 0, s, a, (int)c->P.ncells, cntr + 1, b,
+                       c->P.ntiles, cntr);
+    c->cells_ok = 1;
+    return hip_ok(c, hipGetLastError());
+}
+
 int launch_dem(pibm_ctx *c, hipStream_t s)
 {
     if (c->P.np == 0) return PIBM_OK;
@@ -774,11 +794,13 @@ int step_impl(pibm_ctx *c, int n)
     if (!c->two) {
         for (int k = 0; k < n; ++k) {
             int st;
+            const bool fused = cells_bin_fused(c);
+            if (fused) { PhaseTimer t(c, PIBM_PHASE_BIN); if ((st = launch_cells_bin(c, c->stream, c->tcur))) return st; }
             {
                 PhaseTimer t(c, PIBM_PHASE_MARKERS);
                 if ((st = c->closure ? launch_closure<DIM, SF>(c) : launch_markers<DIM, SF>(c, true))) return st;
             }
-            { PhaseTimer t(c, PIBM_PHASE_BIN); if ((st = launch_bin(c, c->stream, c->tcur))) return st; }
+            if (!fused) { PhaseTimer t(c, PIBM_PHASE_BIN); if ((st = launch_bin(c, c->stream, c->tcur))) return st; }
             { PhaseTimer t(c, PIBM_PHASE_LATTICE); if ((st = launch_lbm<DIM, SF, false>(c))) return st; }
             { PhaseTimer t(c, PIBM_PHASE_DEM); if ((st = launch_dem(c, c->stream))) return st; }
             c->cur ^= 1;

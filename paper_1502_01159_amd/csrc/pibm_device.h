@@ -1937,6 +1937,34 @@ __device__ __forceinline__ void alloc_one_wg(const int *count, int *start, int *
     }
 }
 
+// The cell list and the tile lists of one particle state in one workgroup
+// (few particles, cells and tiles): the phases of k_cells_one_wg and
+// k_bin_one_wg interleaved, four barriers for both.
+__global__ __launch_bounds__(ONE_WG) void k_cells_bin_one_wg(DemArgs d, int ncells, int *ctotal, BinArgs b, int nt,
+                                                             int *btotal)
+{
+    __shared__ int base[BIN_ONE_WG_PARTICLES + 1];
+    const int tid = threadIdx.x;
+    if (block_halted(b.err)) return;
+    for (int i = tid; i < ncells; i += ONE_WG) d.cell_count[i] = 0;
+    for (int i = tid; i < nt; i += ONE_WG) b.tile_count[i] = 0;
+    if (tid == 0) { *ctotal = 0; *btotal = 0; }
+    for (int p = tid; p <= b.np; p += ONE_WG) base[p] = b.gp_base[p];
+    __builtin_amdgcn_s_waitcnt(0);
+    __syncthreads();
+    const int npatch = base[b.np];
+    for (int p = tid; p < d.np; p += ONE_WG) cell_particle<false>(d, p);
+    for (int g = tid; g < npatch; g += ONE_WG) bin_patch<false>(b, g, base);
+    __builtin_amdgcn_s_waitcnt(0);
+    __syncthreads();
+    alloc_one_wg(d.cell_count, d.cell_start, d.cell_fill, ncells, ctotal);
+    alloc_one_wg(b.tile_count, b.tile_start, b.tile_fill, nt, btotal);
+    __builtin_amdgcn_s_waitcnt(0);
+    __syncthreads();
+    for (int p = tid; p < d.np; p += ONE_WG) cell_particle<true>(d, p);
+    for (int g = tid; g < npatch; g += ONE_WG) bin_patch<true>(b, g, base);
+}
+
 __global__ __launch_bounds__(ONE_WG) void k_cells_one_wg(DemArgs a, int ncells, int *total)
 {
     const int tid = threadIdx.x;
